@@ -1,0 +1,211 @@
+"""Benchmark of the ART sweep on one MI355X.
+
+A step is one full batched forward trace (seed, every level's sweep, finalize)
+of the 256^3 lognormal workload with 64 sources of log-uniform luminosity and
+two frequency bins, inputs resident in HBM.  Prints ONE JSON line with
+segments/s (whole job), ms per full trace per source, the plain (one source
+per call) comparison, the roofline of the sweep kernel and the FP64 oracle's
+rate on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload 3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+BYTES_PER_SEGMENT = 40         # 2 x 4 B gather (n_H, x_n) + 4 FP32 read-modify-writes (J_i, F_xyz)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=3)
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-source-per-call timing")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--deterministic", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sweep is not "
+              "sharded across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1711_06277_amd import inputs as I
+    from paper_1711_06277_amd.api import ArtTracer
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+
+    t0 = time.time()
+    wl = I.config(args.workload)
+    if args.deterministic:
+        wl.deterministic = True
+    log(f"[bench] workload {wl.name}: generated in {time.time() - t0:.1f}s")
+
+    tr = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
+                   level0=wl.level0, level_max=wl.level_max, phi_c=wl.phi_c,
+                   tau_term=wl.tau_term, deterministic=wl.deterministic,
+                   max_sources=wl.n_src, block_size=args.block_size,
+                   blocks_per_cu=args.blocks_per_cu, device=dev)
+    nH = torch.from_numpy(wl.n_H).to(dev)
+    xn = torch.from_numpy(wl.x_n).to(dev)
+    pos = torch.from_numpy(wl.src_pos).to(dev)
+    lum = torch.from_numpy(wl.src_lum).to(dev)
+    N = wl.n_cells
+    rate = torch.empty(N, dtype=torch.float32, device=dev)
+    force = torch.empty((3, N), dtype=torch.float32, device=dev)
+    out = (rate, force, None)
+
+    # ---- batched: all sources in one call ----
+    for _ in range(args.warmup):
+        tr.trace(nH, xn, pos, lum, out=out, check=False)
+    rc = tr.sync()
+    if rc != 0:
+        log(f"[bench] device status {rc} after warm-up")
+        sys.exit(1)
+    st = tr.stats(wl.n_src)
+    segments = st.segments
+    log(f"[bench] {segments} segments per trace, {st.n_waves} wave(s), "
+        f"rays in the largest wave {st.rays_max_wave}")
+
+    torch.cuda.synchronize()
+    tr.set_timing(True)
+    sweep_ms = 0.0
+    sweep_launches = 0
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        tr.trace(nH, xn, pos, lum, out=out, check=False)
+        s_ms, n_l, _ = tr.timing()  # synchronises; sums this call's sweep-kernel events
+        sweep_ms += s_ms
+        sweep_launches += n_l
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    tr.set_timing(False)
+    rc = tr.sync()
+    if rc != 0:
+        log(f"[bench] device status {rc}")
+        sys.exit(1)
+    ms_per_step = 1e3 * t_total / args.steps
+    seg_per_s = segments * args.steps / t_total
+    ms_per_source = ms_per_step / wl.n_src
+    log(f"[bench] batched: {ms_per_step:.2f} ms/trace, {seg_per_s:.3e} segments/s, "
+        f"{ms_per_source:.3f} ms per trace per source")
+
+    # roofline of the sweep kernel: algorithmic bytes / summed kernel time
+    sweep_s = sweep_ms / 1e3
+    achieved_gbs = segments * args.steps * BYTES_PER_SEGMENT / sweep_s / 1e9
+    avg_launch_ms = sweep_ms / max(1, sweep_launches)
+
+    # ---- plain: one source per call, same kernel and parameters ----
+    plain = None
+    if not args.no_plain:
+        tp = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
+                       level0=wl.level0, level_max=wl.level_max, phi_c=wl.phi_c,
+                       tau_term=wl.tau_term, deterministic=wl.deterministic, max_sources=1,
+                       block_size=args.block_size, blocks_per_cu=args.blocks_per_cu, device=dev)
+        r1 = torch.empty_like(rate)
+        f1 = torch.empty_like(force)
+        acc_r = torch.zeros_like(rate)
+        acc_f = torch.zeros_like(force)
+        tp.trace(nH, xn, pos[:1], lum[:1], out=(r1, f1, None), check=False)  # warm-up
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        for s in range(wl.n_src):
+            tp.trace(nH, xn, pos[s:s + 1], lum[s:s + 1], out=(r1, f1, None), check=False)
+            acc_r += r1
+            acc_f += f1
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - tp0
+        rc = tp.sync()
+        tp.close()
+        # same accuracy: the sum of plain traces equals the batched trace
+        m = rate.abs() > 1e-8 * float(wl.src_lum.sum())
+        rel = ((acc_r - rate).abs()[m] / rate.abs()[m]).max().item() if m.any() else 0.0
+        plain = {"ms_per_trace": 1e3 * t_plain, "segments_per_s": segments / t_plain,
+                 "ms_per_trace_per_source": 1e3 * t_plain / wl.n_src,
+                 "speedup_batched_over_plain": t_plain / (t_total / args.steps),
+                 "max_rel_diff_rate_vs_batched": rel, "status": rc}
+        log(f"[bench] plain: {1e3 * t_plain:.2f} ms for {wl.n_src} sources, speedup "
+            f"{plain['speedup_batched_over_plain']:.2f}x, max rel diff {rel:.2e}")
+
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe_mib} MiB read + written")
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample (one source) ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        sample = wl.subset([0])
+        tc = time.perf_counter()
+        ref = O.trace_workload(sample)
+        dt = time.perf_counter() - tc
+        seg_cpu = int(ref.segments.sum())
+        cpu = {"value": seg_cpu / dt, "unit": "segments/s", "cores": 1, "kind": "oracle",
+               "sample": f"source 0 of the {wl.n_src}-source {wl.nx}^3 workload "
+                         f"({seg_cpu} segments, {dt:.1f} s, single thread)",
+               "ms_per_trace_per_source": 1e3 * dt}
+        log(f"[bench] oracle: {seg_cpu / dt:.3e} segments/s on one core ({dt:.1f} s)")
+
+    tr.close()
+    result = {
+        "metric": "ray-cell segments/s (batched, one full trace of all sources per step)",
+        "value": seg_per_s,
+        "unit": "segments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "ms_per_trace_per_source": ms_per_source,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 deposits, f64 geometry and optical depth" if not wl.deterministic
+                 else "i64 fixed-point deposits, f64 geometry and optical depth",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "n_sources": wl.n_src,
+                   "n_bins": wl.n_bins, "level0": wl.level0, "level_max": wl.level_max,
+                   "m_ray": wl.phi_c, "tau_term": wl.tau_term,
+                   "deposit": "deterministic" if wl.deterministic else "atomic",
+                   "segments_per_trace": segments, "waves": st.n_waves},
+        "plain": plain,
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_sweep (one launch per HEALPix level)",
+                     "bytes_per_segment": BYTES_PER_SEGMENT,
+                     "sweep_ms_per_step": sweep_ms / args.steps,
+                     "avg_launch_ms": avg_launch_ms},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * art.h -- C ABI of the MI355X (gfx950) adaptive ray tracing (ART) sweep.
+ *
+ * The sweep follows Kim, Kim, Ostriker & Skinner (2017), Sec. 2.1 "Adaptive Ray
+ * Tracing": photon packets leave each point source along HEALPix directions
+ * (N_ray(l) = 12*4^l equal-area pixels, packet luminosity L/N_ray(l0)), are
+ * marched cell by cell through a uniform Cartesian grid, lose
+ * Delta L = L_in (1 - e^{-Delta tau}) with Delta tau = chi Delta r in every cell
+ * they cross, deposit that luminosity and the momentum n Delta L / c there
+ * (Eqs. e:RT2, e:Erad, e:Frad), split into the four HEALPix children at
+ * r_max(l) = sqrt(3/(pi m_ray)) 2^l dx, and end at the domain boundary or once
+ * the optical depth from the source exceeds tau_term in every frequency bin.
+ * The opacities are those of Sec. 2.3: chi_i = n_H (x_n sigma_H + sigma_d) for
+ * the ionizing bin, chi_n = n_H sigma_d for the non-ionizing bin.
+ *
+ * Units: cell size dx = 1, cell volume 1, c = 1, h nu_i = 1.
+ * Grid layout: cell (i, j, k) occupies [i,i+1) x [j,j+1) x [k,k+1); a field is a
+ * flat array of nx*ny*nz values with x fastest: index (k*ny + j)*nx + i.
+ *
+ * Memory ownership: every pointer argument of art_trace / art_trace_adjoint is
+ * DEVICE memory owned by the caller.  The library owns only its workspace (ray
+ * pool, counters, accumulators), allocated in art_create and freed in
+ * art_destroy.  Outputs are overwritten, never accumulated.
+ *
+ * Streams: art_trace and art_trace_adjoint only enqueue kernels on the
+ * context's stream (no host synchronisation, no allocation, no memset nodes),
+ * so they can be captured into a HIP graph.  Device-side failures (ray pool
+ * overflow, a source outside the domain, a broken destroy count) are recorded
+ * in a device status word and reported by art_sync / art_get_stats, which
+ * synchronise the stream.
+ *
+ * Errors: every function returns ART_OK (0) or a negative ART_ERR_* code; no
+ * exception or abort crosses the ABI.  art_strerror names a code.
+ */
+#ifndef ART_H
+#define ART_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ART_OK 0
+#define ART_ERR_INVALID_ARG (-1)      /* bad size, level, pointer or parameter */
+#define ART_ERR_HIP (-2)              /* a HIP runtime call failed */
+#define ART_ERR_OUT_OF_MEMORY (-3)    /* workspace allocation failed in art_create */
+#define ART_ERR_QUEUE_OVERFLOW (-4)   /* device: the ray pool filled up (no ray is dropped silently) */
+#define ART_ERR_SOURCE_OUTSIDE (-5)   /* device: a source position lies outside the domain */
+#define ART_ERR_DESTROY_COUNT (-6)    /* device: ended rays do not add up to N_src*12*4^level_max */
+#define ART_ERR_NO_FORWARD (-7)       /* adjoint requested on a context built without adjoint support */
+
+#define ART_DEPOSIT_ATOMIC 0          /* FP32 hardware atomics (fast, order-dependent rounding) */
+#define ART_DEPOSIT_DETERMINISTIC 1   /* 64-bit fixed-point integer sums: bitwise reproducible */
+
+#define ART_MAX_LEVELS 16
+#define ART_MAX_BINS 2
+
+/* Method parameters (Sec. 2.1, Sec. 2.3). */
+typedef struct {
+    int level0;          /* initial HEALPix level l0 (12*4^l0 rays per source) */
+    int level_max;       /* deepest level; rays at level_max never split; < ART_MAX_LEVELS */
+    double phi_c;        /* m_ray: split when (dx/r)^2 < m_ray * Omega_ray */
+    double tau_term;     /* destroy a ray once tau_b > tau_term in every bin */
+    double s_H;          /* sigma_H * dx in code units: ionizing gas opacity per unit n_H x_n */
+    double s_d;          /* sigma_d * dx in code units: dust opacity per unit n_H */
+    int n_bins;          /* 1 (ionizing only) or 2 (ionizing, non-ionizing) */
+    double rot[9];       /* row-major rotation applied to every HEALPix direction */
+    int deposit_mode;    /* ART_DEPOSIT_ATOMIC or ART_DEPOSIT_DETERMINISTIC */
+} art_params;
+
+/* Workspace and launch options fixed at art_create. */
+typedef struct {
+    int max_sources;         /* largest n_src accepted by art_trace */
+    int enable_adjoint;      /* 1: also allocate the adjoint workspace */
+    int64_t pool_rays;       /* ray-pool capacity (rays per source wave); 0 = size automatically */
+    double pool_mem_fraction;/* automatic sizing: at most this fraction of free HBM (0 -> 0.5) */
+    int block_size;          /* threads per workgroup of the sweep kernels (64, 128, 192 or 256; 0 -> 256) */
+    int blocks_per_cu;       /* workgroups per CU launched for each sweep (0 -> 4) */
+} art_options;
+
+/* Per-trace statistics (host copy).  Per-source arrays are indexed [src][level]
+ * or [src][bin] and hold the first min(n_src, stats_sources) sources. */
+typedef struct {
+    int status;                    /* ART_OK or the first device-side error of the last call */
+    int n_src;                     /* sources in the last art_trace */
+    int n_waves;                   /* source waves the last art_trace was split into */
+    uint64_t segments;             /* ray-cell segments deposited (all sources) */
+    uint64_t destroy;              /* sum over ended rays of 4^(level_max - level) */
+    uint64_t destroy_expected;     /* n_src * 12 * 4^level_max */
+    uint64_t rays_max_wave;        /* largest number of rays held by one source wave */
+    uint64_t created[ART_MAX_LEVELS], split[ART_MAX_LEVELS];
+    uint64_t exited[ART_MAX_LEVELS], terminated[ART_MAX_LEVELS];
+} art_stats;
+
+typedef struct art_ctx art_ctx;
+
+/* Create a context for an nx*ny*nz grid.  `stream` is a hipStream_t (NULL = the
+ * null stream).  Allocates the workspace; returns ART_ERR_OUT_OF_MEMORY if it
+ * does not fit.  On success *ctx is owned by the caller until art_destroy. */
+int art_create(art_ctx **ctx, int nx, int ny, int nz, const art_params *params,
+               const art_options *opts, void *stream);
+
+/* Change the stream later calls are enqueued on. */
+int art_set_stream(art_ctx *ctx, void *stream);
+
+/* Forward ART sweep (Sec. 2.1).
+ *   n_H     [N]        total hydrogen density per cell (float, >= 0)
+ *   x_n     [N]        neutral fraction per cell (float, in [0, 1])
+ *   src_pos [n_src][3] source positions in cell units (double), inside [0,nx)x[0,ny)x[0,nz)
+ *   src_lum [n_src][n_bins] source luminosity per bin (float, >= 0)
+ *   rate    [N]        out: photoionizations per unit time, s_H x_n n_H J_0 (Eq. e:photrate2)
+ *   force   [3][N]     out: absorbed momentum per unit time, sum over bins of
+ *                      Delta L n (chi F / c, Eq. e:radforce), structure of arrays
+ *   J       [n_bins][N] out (may be NULL): sum of L_in dr (1-e^{-dtau})/dtau per cell,
+ *                      i.e. c E dV of Eq. e:Erad with the chi -> 0 limit taken
+ * All sources share one ray pool; they are traced together in waves of as many
+ * sources as the pool holds.  Asynchronous on the context's stream. */
+int art_trace(art_ctx *ctx, const float *n_H, const float *x_n, const double *src_pos,
+              const float *src_lum, int n_src, float *rate, float *force, float *J);
+
+/* Reverse-mode derivative of loss = sum_c g_rate[c] rate[c] + sum_c g_force[.][c] . force[.][c]
+ * with respect to n_H and x_n, holding the ray tree of the forward sweep fixed
+ * (the same splits, exits and optical-depth terminations).
+ *   g_rate [N], g_force [3][N]  in (device, float)
+ *   g_nH [N], g_xn [N]          out (device, float), overwritten
+ * Same n_H, x_n and sources as the forward sweep.  Requires enable_adjoint.
+ * Recomputes the ray tree and every segment's optical depth instead of storing
+ * segments, so it can run without a preceding art_trace. */
+int art_trace_adjoint(art_ctx *ctx, const float *n_H, const float *x_n, const double *src_pos,
+                      const float *src_lum, int n_src, const float *g_rate,
+                      const float *g_force, float *g_nH, float *g_xn);
+
+/* Synchronise the stream and return the device status of the last call. */
+int art_sync(art_ctx *ctx);
+
+/* Synchronise and copy the statistics of the last art_trace (and per-source
+ * arrays, each [stats_sources][ART_MAX_LEVELS] or [stats_sources][ART_MAX_BINS],
+ * any of which may be NULL). */
+int art_get_stats(art_ctx *ctx, art_stats *out, int stats_sources, uint32_t *src_created,
+                  uint32_t *src_split, uint32_t *src_exited, uint32_t *src_terminated,
+                  double *src_escaped, double *src_residual, uint64_t *src_segments);
+
+/* Time the forward sweep on the given inputs for each candidate launch shape
+ * (block_size x blocks_per_cu from the built-in list) and keep the fastest in
+ * the context; writes the chosen pair and its time in milliseconds.  Runs the
+ * sweep several times and synchronises; outputs hold the last run. */
+int art_autotune(art_ctx *ctx, const float *n_H, const float *x_n, const double *src_pos,
+                 const float *src_lum, int n_src, float *rate, float *force,
+                 int *best_block_size, int *best_blocks_per_cu, float *best_ms);
+
+/* Average duration in ms of the per-level sweep launches of the last forward
+ * call (HIP events on the context's stream; enable with art_set_timing). */
+int art_set_timing(art_ctx *ctx, int enable);
+int art_get_timing(art_ctx *ctx, float *sweep_ms_total, int *sweep_launches, float *total_ms);
+
+void art_destroy(art_ctx *ctx);
+const char *art_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ART_H */

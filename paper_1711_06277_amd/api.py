@@ -1,0 +1,223 @@
+"""PyTorch-facing wrapper of the HIP ART sweep.
+
+PyTorch supplies device memory and the stream; every step of the sweep runs in
+``libart.so`` through the C ABI (``_abi``).  There is no CPU path: without the
+built library or a GPU these calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+TAU_TERM_1E10 = math.log(1.0e10)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, device):
+    t = torch.as_tensor(t, dtype=dtype, device=device)
+    return t.contiguous()
+
+
+@dataclass
+class TraceStats:
+    status: int
+    n_src: int
+    n_waves: int
+    segments: int
+    destroy: int
+    destroy_expected: int
+    rays_max_wave: int
+    created: np.ndarray      # [16] totals per level
+    split: np.ndarray
+    exited: np.ndarray
+    terminated: np.ndarray
+    src_created: np.ndarray  # [n_src, 16]
+    src_split: np.ndarray
+    src_exited: np.ndarray
+    src_terminated: np.ndarray
+    src_escaped: np.ndarray  # [n_src, 2]
+    src_residual: np.ndarray
+    src_segments: np.ndarray  # [n_src]
+
+
+class ArtTracer:
+    """One ART context: grid shape, method parameters and the device workspace.
+
+    Parameters follow Sec. 2.1 / 2.3 of the paper: ``level0`` (initial HEALPix
+    level), ``level_max``, ``phi_c`` (m_ray), ``tau_term`` (termination optical
+    depth), ``s_H`` / ``s_d`` (gas / dust opacity per cell length per unit
+    density), ``n_bins`` (1: ionizing, 2: + non-ionizing).
+    """
+
+    def __init__(self, nx, ny, nz, *, s_H, s_d, n_bins=1, level0=2, level_max=13, phi_c=4.0,
+                 tau_term=TAU_TERM_1E10, rot=None, deterministic=False, max_sources=1,
+                 enable_adjoint=False, pool_rays=0, pool_mem_fraction=0.5, block_size=0,
+                 blocks_per_cu=0, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("ArtTracer needs a GPU: the sweep has no CPU implementation")
+        self.device = torch.device(device)
+        self.shape = (int(nx), int(ny), int(nz))
+        self.N = int(nx) * int(ny) * int(nz)
+        self.n_bins = int(n_bins)
+        self.s_H, self.s_d = float(s_H), float(s_d)
+        self.max_sources = int(max_sources)
+        p = A.art_params()
+        p.level0, p.level_max = int(level0), int(level_max)
+        p.phi_c, p.tau_term = float(phi_c), float(tau_term)
+        p.s_H, p.s_d = self.s_H, self.s_d
+        p.n_bins = self.n_bins
+        r = np.eye(3) if rot is None else np.asarray(rot, dtype=np.float64).reshape(3, 3)
+        for i, x in enumerate(r.reshape(-1)):
+            p.rot[i] = float(x)
+        p.deposit_mode = A.ART_DEPOSIT_DETERMINISTIC if deterministic else A.ART_DEPOSIT_ATOMIC
+        o = A.art_options()
+        o.max_sources = self.max_sources
+        o.enable_adjoint = 1 if enable_adjoint else 0
+        o.pool_rays = int(pool_rays)
+        o.pool_mem_fraction = float(pool_mem_fraction)
+        o.block_size, o.blocks_per_cu = int(block_size), int(blocks_per_cu)
+        self.params, self.options = p, o
+        with torch.cuda.device(self.device):
+            self._ctx = A.art_create(nx, ny, nz, p, o, torch.cuda.current_stream().cuda_stream)
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_ctx", None):
+            A.art_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        A.art_set_stream(self._ctx, torch.cuda.current_stream(self.device).cuda_stream)
+
+    # -- calls ---------------------------------------------------------------
+    def trace(self, n_H, x_n, src_pos, src_lum, *, want_J=False, out=None, check=True):
+        """Forward sweep.  Returns (rate [N], force [3, N]) or (rate, force, J)."""
+        d = self.device
+        n_H = _dev(n_H, torch.float32, d).reshape(-1)
+        x_n = _dev(x_n, torch.float32, d).reshape(-1)
+        src_pos = _dev(src_pos, torch.float64, d).reshape(-1, 3)
+        n_src = src_pos.shape[0]
+        src_lum = _dev(src_lum, torch.float32, d).reshape(n_src, self.n_bins)
+        if n_H.numel() != self.N or x_n.numel() != self.N:
+            raise ValueError("field size does not match the grid")
+        if out is None:
+            rate = torch.empty(self.N, dtype=torch.float32, device=d)
+            force = torch.empty((3, self.N), dtype=torch.float32, device=d)
+            J = torch.empty((self.n_bins, self.N), dtype=torch.float32, device=d) if want_J else None
+        else:
+            rate, force, J = out
+        self._stream()
+        A.art_trace(self._ctx, _ptr(n_H), _ptr(x_n), _ptr(src_pos), _ptr(src_lum), n_src,
+                    _ptr(rate), _ptr(force), _ptr(J))
+        if check:
+            A.check(A.art_sync(self._ctx), "art_trace (device)")
+        return (rate, force, J) if want_J else (rate, force)
+
+    def adjoint(self, n_H, x_n, src_pos, src_lum, g_rate, g_force, *, out=None, check=True):
+        """dL/dn_H, dL/dx_n for L = <g_rate, rate> + <g_force, force>."""
+        d = self.device
+        n_H = _dev(n_H, torch.float32, d).reshape(-1)
+        x_n = _dev(x_n, torch.float32, d).reshape(-1)
+        src_pos = _dev(src_pos, torch.float64, d).reshape(-1, 3)
+        n_src = src_pos.shape[0]
+        src_lum = _dev(src_lum, torch.float32, d).reshape(n_src, self.n_bins)
+        g_rate = _dev(g_rate, torch.float32, d).reshape(-1)
+        g_force = _dev(g_force, torch.float32, d).reshape(3, -1)
+        if out is None:
+            g_nH = torch.empty(self.N, dtype=torch.float32, device=d)
+            g_xn = torch.empty(self.N, dtype=torch.float32, device=d)
+        else:
+            g_nH, g_xn = out
+        self._stream()
+        A.art_trace_adjoint(self._ctx, _ptr(n_H), _ptr(x_n), _ptr(src_pos), _ptr(src_lum), n_src,
+                            _ptr(g_rate), _ptr(g_force), _ptr(g_nH), _ptr(g_xn))
+        if check:
+            A.check(A.art_sync(self._ctx), "art_trace_adjoint (device)")
+        return g_nH, g_xn
+
+    def sync(self) -> int:
+        return A.art_sync(self._ctx)
+
+    def stats(self, n_src_stats=None) -> TraceStats:
+        ns = self.max_sources if n_src_stats is None else int(n_src_stats)
+        L = A.ART_MAX_LEVELS
+        arr = {k: np.zeros((ns, L), dtype=np.uint32) for k in ("c", "s", "e", "t")}
+        esc = np.zeros((ns, 2))
+        res = np.zeros((ns, 2))
+        seg = np.zeros(ns, dtype=np.uint64)
+        st = A.art_get_stats(self._ctx, ns, *(arr[k].ctypes.data for k in "cset"),
+                             esc.ctypes.data, res.ctypes.data, seg.ctypes.data)
+        n = min(ns, st.n_src)
+        return TraceStats(
+            status=st.status, n_src=st.n_src, n_waves=st.n_waves, segments=int(st.segments),
+            destroy=int(st.destroy), destroy_expected=int(st.destroy_expected),
+            rays_max_wave=int(st.rays_max_wave),
+            created=np.array(st.created[:], dtype=np.int64), split=np.array(st.split[:], dtype=np.int64),
+            exited=np.array(st.exited[:], dtype=np.int64),
+            terminated=np.array(st.terminated[:], dtype=np.int64),
+            src_created=arr["c"][:n].astype(np.int64), src_split=arr["s"][:n].astype(np.int64),
+            src_exited=arr["e"][:n].astype(np.int64), src_terminated=arr["t"][:n].astype(np.int64),
+            src_escaped=esc[:n, : self.n_bins], src_residual=res[:n, : self.n_bins],
+            src_segments=seg[:n].astype(np.int64))
+
+    def autotune(self, n_H, x_n, src_pos, src_lum):
+        d = self.device
+        n_H = _dev(n_H, torch.float32, d).reshape(-1)
+        x_n = _dev(x_n, torch.float32, d).reshape(-1)
+        src_pos = _dev(src_pos, torch.float64, d).reshape(-1, 3)
+        n_src = src_pos.shape[0]
+        src_lum = _dev(src_lum, torch.float32, d).reshape(n_src, self.n_bins)
+        rate = torch.empty(self.N, dtype=torch.float32, device=d)
+        force = torch.empty((3, self.N), dtype=torch.float32, device=d)
+        self._stream()
+        return A.art_autotune(self._ctx, _ptr(n_H), _ptr(x_n), _ptr(src_pos), _ptr(src_lum), n_src,
+                              _ptr(rate), _ptr(force))
+
+    def set_timing(self, enable: bool):
+        A.art_set_timing(self._ctx, enable)
+
+    def timing(self):
+        """(sum of sweep-kernel durations in ms, number of sweep launches, whole call ms)."""
+        return A.art_get_timing(self._ctx)
+
+
+class ArtTrace(torch.autograd.Function):
+    """(rate, force) = ART sweep of (n_H, x_n); backward runs the adjoint sweep."""
+
+    @staticmethod
+    def forward(ctx, n_H, x_n, tracer: ArtTracer, src_pos, src_lum):
+        rate, force = tracer.trace(n_H, x_n, src_pos, src_lum)
+        ctx.tracer = tracer
+        ctx.save_for_backward(n_H, x_n, src_pos, src_lum)
+        return rate, force
+
+    @staticmethod
+    def backward(ctx, g_rate, g_force):
+        n_H, x_n, src_pos, src_lum = ctx.saved_tensors
+        tr = ctx.tracer
+        if g_rate is None:
+            g_rate = torch.zeros(tr.N, dtype=torch.float32, device=n_H.device)
+        if g_force is None:
+            g_force = torch.zeros((3, tr.N), dtype=torch.float32, device=n_H.device)
+        g_nH, g_xn = tr.adjoint(n_H, x_n, src_pos, src_lum, g_rate, g_force)
+        return g_nH.view_as(n_H), g_xn.view_as(x_n), None, None, None
+
+
+def art_trace(n_H, x_n, tracer: ArtTracer, src_pos, src_lum):
+    """Differentiable forward sweep: returns (rate, force)."""
+    return ArtTrace.apply(n_H, x_n, tracer, src_pos, src_lum)

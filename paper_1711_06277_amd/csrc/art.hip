@@ -1,0 +1,1225 @@
+// art.hip -- MI355X (gfx950) implementation of the ART sweep behind the C ABI
+// declared in include/art.h.
+//
+// Design (one GPU, one process):
+//   * All sources of a call share one ray pool.  Rays live in per-HEALPix-level
+//     segments of the pool, level l0 first; the children of level l are appended
+//     behind level l while it is swept, so the pool holds the whole ray tree of a
+//     source wave (and doubles as the adjoint's tape).  Sources are admitted in
+//     waves sized so that the tree of a wave fits the pool.
+//   * One persistent-style launch per level: a grid of resident workgroups whose
+//     wavefronts claim 64-ray chunks from the level's shared multi-source queue
+//     with one atomic per chunk, one ray per lane.  Rays of one level have the
+//     same radial shell [r_max(l-1), r_max(l)], so the lanes of a wavefront do
+//     similar amounts of work.
+//   * Geometry, tau and all tree decisions in FP64; the per-segment deposit
+//     arithmetic in FP32; deposits by hardware FP32 atomics into L2, or by 64-bit
+//     fixed-point integer atomics in the deterministic mode (integer sums do not
+//     depend on the order, so results are bitwise reproducible).
+//   * The destroy counter of Sec. 2.2 (a ray ended at level l adds
+//     4^(l_max - l)) is kept as a device-side completeness check of the tree.
+//   * No allocation, host synchronisation or memset node inside art_trace /
+//     art_trace_adjoint: they can be captured into a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "art_device.h"
+
+using namespace art;
+
+namespace {
+
+// --------------------------------------------------------------------------
+// Device state
+// --------------------------------------------------------------------------
+
+// Counters of the current source wave, reset by the seed kernel.
+struct WaveCounters {
+    uint32_t head[ART_MAX_LEVELS + 1];      // forward chunk claims per level
+    uint32_t tail[ART_MAX_LEVELS + 1];      // rays per level (children appended here)
+    uint32_t adj_head[ART_MAX_LEVELS + 1];  // adjoint chunk claims per level
+    uint64_t off[ART_MAX_LEVELS + 1];       // pool offset of each level
+};
+
+// Counters of a whole call.
+struct CallCounters {
+    unsigned long long destroy;
+    unsigned long long segments;
+    unsigned long long rays_wave_max;
+    uint32_t status;
+    uint32_t pad;
+    double scale, inv_scale;      // forward fixed point: 2^60 / L_total
+    double gscale, inv_gscale;    // adjoint fixed point
+};
+
+struct Counters {
+    WaveCounters w;
+    CallCounters c;
+};
+
+// The ray pool, structure of arrays.
+struct Pool {
+    uint32_t* src;    // source index
+    uint32_t* pix;    // nested pixel at the ray's level
+    double* tau;      // [cap][2]: optical depth from the source at the ray's start
+    uint32_t* child;  // pool index of the first of the four children (or kNoChild)
+    double* G;        // [cap][2]: adjoint, loss contributed downstream of the start
+    uint64_t cap;
+};
+
+// Per-source statistics, [max_src][ART_MAX_LEVELS] / [max_src][2] / [max_src].
+struct SrcStats {
+    uint32_t *created, *split, *exited, *term;
+    double *escaped, *residual;
+    unsigned long long* segments;
+};
+
+struct SweepArgs {
+    Geo g;
+    const float* nH;
+    const float* xn;
+    const double* src_pos;
+    const float* src_lum;
+    Pool pool;
+    Counters* ct;
+    SrcStats st;
+    // FP32 deposit targets (atomic mode)
+    float* J0;
+    float* J1;   // may be null
+    float* F;    // [3][N]
+    // fixed-point targets (deterministic mode): [5][N] = J0, J1, Fx, Fy, Fz
+    unsigned long long* det;
+    uint32_t N;
+    uint32_t n_src;
+};
+
+struct AdjArgs {
+    Geo g;
+    const float* nH;
+    const float* xn;
+    const double* src_pos;
+    const float* src_lum;
+    const float* w;   // [N]
+    const float* v;   // [3][N]
+    Pool pool;
+    Counters* ct;
+    double* gk;                // [2][N] dL/dkappa_b, FP64 atomics
+    unsigned long long* gdet;  // [2][N] fixed point
+    uint32_t N;
+    uint32_t n_src;
+};
+
+__device__ __forceinline__ void fx_add(unsigned long long* p, double v, double scale) {
+    const long long q = __double2ll_rn(v * scale);
+    if (q != 0) atomicAdd(p, (unsigned long long)q);
+}
+
+// --------------------------------------------------------------------------
+// Small kernels
+// --------------------------------------------------------------------------
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+__global__ void k_fill_f32(float* p, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+__global__ void k_fill_f64(double* p, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// Reset the call counters; in deterministic mode also set the fixed-point
+// scale 2^60 / L_total (a cell can receive at most ~sqrt(3) L_total of J).
+__global__ void k_begin_call(Counters* ct, const float* src_lum, int n_lum) {
+    __shared__ double part[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n_lum; i += blockDim.x) s += fabs((double)src_lum[i]);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double L = part[0] > 0.0 ? part[0] : 1.0;
+        ct->c.destroy = 0ull;
+        ct->c.segments = 0ull;
+        ct->c.rays_wave_max = 0ull;
+        ct->c.status = 0u;
+        ct->c.scale = ldexp(1.0, 60) / L;
+        ct->c.inv_scale = L * ldexp(1.0, -60);
+    }
+}
+
+// Fixed-point scale of the adjoint: |dL/dkappa| per cell is bounded by a few
+// times L_total (max w + sqrt(3) max |v|), see the adjoint kernel.
+__global__ void k_adj_scale(Counters* ct, const float* w, const float* v, uint64_t N,
+                            const float* src_lum, int n_lum, float* scratch_max) {
+    __shared__ float part[256];
+    float m = 0.0f;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        m = fmaxf(m, fabsf(w[i]));
+        const float vv = fabsf(v[i]) + fabsf(v[N + i]) + fabsf(v[2 * N + i]);
+        m = fmaxf(m, 1.7320508f * vv);
+    }
+    part[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] = fmaxf(part[threadIdx.x], part[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax((unsigned int*)scratch_max, __float_as_uint(part[0]));
+    (void)ct;
+    (void)src_lum;
+    (void)n_lum;
+}
+
+__global__ void k_adj_scale_final(Counters* ct, const float* src_lum, int n_lum, const float* scratch_max,
+                                  double s_H_max) {
+    if (threadIdx.x != 0) return;
+    double L = 0.0;
+    for (int i = 0; i < n_lum; ++i) L += fabs((double)src_lum[i]);
+    if (!(L > 0.0)) L = 1.0;
+    double W = (double)(*scratch_max) * (1.0 + s_H_max);
+    if (!(W > 0.0)) W = 1.0;
+    const double bound = 8.0 * W * L;
+    ct->c.gscale = ldexp(1.0, 58) / bound;
+    ct->c.inv_gscale = bound * ldexp(1.0, -58);
+}
+
+// Seed a source wave: 12*4^l0 rays per source at level l0 (Sec. 2.1), source
+// major and nested pixel minor, so that a wavefront holds 64 neighbouring
+// directions of one source.  Resets the wave counters.
+__global__ void k_seed(Pool pool, Counters* ct, int level0, int src0, int n_wave, int n_bins,
+                       int want_child) {
+    const uint32_t per_src = 12u << (2 * level0);
+    const uint64_t n = (uint64_t)per_src * (uint64_t)n_wave;
+    if (blockIdx.x == 0 && threadIdx.x <= ART_MAX_LEVELS) {
+        const int l = threadIdx.x;
+        ct->w.head[l] = 0u;
+        ct->w.adj_head[l] = 0u;
+        ct->w.tail[l] = (l == level0) ? (uint32_t)n : 0u;
+        ct->w.off[l] = 0ull;
+    }
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        pool.src[i] = (uint32_t)src0 + (uint32_t)(i / per_src);
+        pool.pix[i] = (uint32_t)(i % per_src);
+        pool.tau[2 * i] = 0.0;
+        pool.tau[2 * i + 1] = 0.0;
+        if (want_child) pool.child[i] = kNoChild;
+    }
+    (void)n_bins;
+}
+
+// --------------------------------------------------------------------------
+// Forward sweep of one level
+// --------------------------------------------------------------------------
+
+// DET: fixed-point deposits.  FULL: deposit force (and J1); otherwise only J0
+// (the tape pass of the adjoint needs J0 for the explicit rate term).
+template <int NB, bool DET, bool FULL>
+__global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
+    const Geo& g = a.g;
+    Counters* ct = a.ct;
+    const int lane = lane_id();
+    // After a pool overflow the tree is incomplete and some slots were never
+    // written: do no further work (the error is reported on synchronisation).
+    if (ct->c.status & kStOverflow) return;
+    const uint64_t off = ct->w.off[level];
+    const uint32_t n_tail = ct->w.tail[level];
+    const uint32_t n_level = (uint32_t)std::min<uint64_t>(n_tail, a.pool.cap > off ? a.pool.cap - off : 0);
+    const uint64_t off_next = off + n_level;
+    const int next = level + 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && next <= ART_MAX_LEVELS) ct->w.off[next] = off_next;
+    const uint32_t N = a.N;
+    const double scale = DET ? ct->c.scale : 0.0;
+    const float lnom_scale = ldexpf(1.0f / 12.0f, -2 * level);  // 1 / N_ray(l)
+    const unsigned long long dweight = 1ull << (2 * (g.level_max - level));
+
+    for (;;) {
+        // Every lane claims one ray.  The uniform-address atomic is combined by
+        // the compiler into one atomic per wavefront (consecutive indices), and
+        // the loop exit is a wave-uniform ballot, so the loop stays a single
+        // convergent loop (no lane waits on a value another lane computes under
+        // a divergent branch).
+        const uint32_t li = atomicAdd(&ct->w.head[level], 1u);
+        const bool active = li < n_level;
+        if (__ballot(active) == 0ull) break;
+        const uint64_t slot = off + (active ? li : 0u);
+
+        uint32_t src = 0, pix = 0;
+        int end = kExit;
+        uint32_t nseg = 0;
+        double left[NB];
+        double tau[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            left[b] = 0.0;
+            tau[b] = 0.0;
+        }
+        bool bad_src = false, stuck = false;
+        if (active) {
+            src = a.pool.src[slot];
+            pix = a.pool.pix[slot];
+            if (src >= a.n_src) {  // never happens for a written slot; keeps reads in bounds
+                bad_src = true;
+                src = 0;
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b) tau[b] = a.pool.tau[2 * slot + b];
+            Ray r;
+            ray_setup(g, a.src_pos, src, level, pix, r);
+            float lnom[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) lnom[b] = a.src_lum[(uint64_t)src * NB + b] * lnom_scale;
+            if (bad_src || !source_inside(g, r.xs)) {
+                bad_src = true;
+                end = kExit;
+            } else if (r.starts_outside) {
+                end = kExit;
+            } else {
+                const float nx = (float)r.n[0], ny = (float)r.n[1], nz = (float)r.n[2];
+                end = march<NB>(g, a.nH, a.xn, r, tau, &stuck,
+                    [&](uint32_t c, double dr, const double (&dtau)[NB], const double (&tin)[NB]) {
+                        const float drf = (float)dr;
+                        float dLs = 0.0f;
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) {
+                            const float x = (float)dtau[b];
+                            const float Lin = lnom[b] * __expf(-(float)tin[b]);
+                            float ph, om;
+                            absorb_factors(x, ph, om);
+                            dLs += Lin * om;
+                            const float jv = Lin * drf * ph;
+                            if (b == 0) {
+                                if (DET) fx_add(&a.det[c], (double)jv, scale);
+                                else unsafeAtomicAdd(&a.J0[c], jv);
+                            } else if (FULL) {
+                                if (DET) fx_add(&a.det[(uint64_t)N + c], (double)jv, scale);
+                                else if (a.J1) unsafeAtomicAdd(&a.J1[c], jv);
+                            }
+                        }
+                        if (FULL) {
+                            if (DET) {
+                                fx_add(&a.det[2ull * N + c], (double)(nx * dLs), scale);
+                                fx_add(&a.det[3ull * N + c], (double)(ny * dLs), scale);
+                                fx_add(&a.det[4ull * N + c], (double)(nz * dLs), scale);
+                            } else {
+                                unsafeAtomicAdd(&a.F[c], nx * dLs);
+                                unsafeAtomicAdd(&a.F[(uint64_t)N + c], ny * dLs);
+                                unsafeAtomicAdd(&a.F[2ull * N + c], nz * dLs);
+                            }
+                        }
+                        ++nseg;
+                    });
+            }
+            if (end != kSplit) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    left[b] = (double)a.src_lum[(uint64_t)src * NB + b] / (12.0 * ldexp(1.0, 2 * level)) *
+                              exp(-tau[b]);
+            }
+        }
+        if (__ballot(bad_src)) {
+            if (lane == 0) atomicOr(&ct->c.status, (uint32_t)kStOutside);
+        }
+        if (__ballot(stuck)) {
+            if (lane == 0) atomicOr(&ct->c.status, (uint32_t)kStStuck);
+        }
+
+        // ---- children: four per splitting ray, appended to level l+1 ----
+        const bool is_split = active && end == kSplit;
+        const bool is_exit = active && end == kExit;
+        const bool is_term = active && end == kTerm;
+        const uint32_t nsplit = (uint32_t)__popcll(__ballot(is_split));
+        if (is_split) {
+            const uint64_t cs = off_next + (uint64_t)atomicAdd(&ct->w.tail[next], 4u);
+            if (cs + 4 <= a.pool.cap) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    a.pool.src[cs + k] = src;
+                    a.pool.pix[cs + k] = 4u * pix + (uint32_t)k;
+                    a.pool.tau[2 * (cs + k)] = tau[0];
+                    a.pool.tau[2 * (cs + k) + 1] = (NB > 1) ? tau[NB - 1] : 0.0;
+                    if (a.pool.child) a.pool.child[cs + k] = kNoChild;
+                }
+                if (a.pool.child) a.pool.child[slot] = (uint32_t)cs;
+            } else {
+                atomicOr(&ct->c.status, (uint32_t)kStOverflow);
+            }
+        }
+
+        // ---- statistics: one atomic per counter per wavefront when the
+        //      chunk belongs to a single source (the common case) ----
+        const uint32_t s_first = (uint32_t)__builtin_amdgcn_readfirstlane((int)src);
+        const bool mixed = __ballot(active && src != s_first) != 0ull;
+        const uint32_t n_act = (uint32_t)__popcll(__ballot(active));
+        const uint32_t n_exit = (uint32_t)__popcll(__ballot(is_exit));
+        const uint32_t n_term = (uint32_t)__popcll(__ballot(is_term));
+        const unsigned long long seg_sum = wave_sum((unsigned long long)nseg);
+        if (lane == 0) {
+            atomicAdd(&ct->c.destroy, (unsigned long long)(n_exit + n_term) * dweight);
+            atomicAdd(&ct->c.segments, seg_sum);
+        }
+        if (!mixed) {
+            double esc[NB], res[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                esc[b] = wave_sum(is_exit ? left[b] : 0.0);
+                res[b] = wave_sum(is_term ? left[b] : 0.0);
+            }
+            if (lane == 0) {
+                const uint64_t sl = (uint64_t)s_first * ART_MAX_LEVELS + level;
+                atomicAdd(&a.st.created[sl], n_act);
+                if (nsplit) atomicAdd(&a.st.split[sl], nsplit);
+                if (n_exit) atomicAdd(&a.st.exited[sl], n_exit);
+                if (n_term) atomicAdd(&a.st.term[sl], n_term);
+                atomicAdd(&a.st.segments[s_first], seg_sum);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (n_exit) unsafeAtomicAdd(&a.st.escaped[2 * (uint64_t)s_first + b], esc[b]);
+                    if (n_term) unsafeAtomicAdd(&a.st.residual[2 * (uint64_t)s_first + b], res[b]);
+                }
+            }
+        } else if (active) {
+            const uint64_t sl = (uint64_t)src * ART_MAX_LEVELS + level;
+            atomicAdd(&a.st.created[sl], 1u);
+            if (is_split) atomicAdd(&a.st.split[sl], 1u);
+            if (is_exit) atomicAdd(&a.st.exited[sl], 1u);
+            if (is_term) atomicAdd(&a.st.term[sl], 1u);
+            atomicAdd(&a.st.segments[src], (unsigned long long)nseg);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (is_exit) unsafeAtomicAdd(&a.st.escaped[2 * (uint64_t)src + b], left[b]);
+                if (is_term) unsafeAtomicAdd(&a.st.residual[2 * (uint64_t)src + b], left[b]);
+            }
+        }
+    }
+}
+
+// After the deepest level of a wave: record the number of rays the wave held.
+__global__ void k_end_wave(Counters* ct, int level0, int level_max) {
+    if (threadIdx.x != 0) return;
+    unsigned long long tot = 0;
+    for (int l = level0; l <= level_max + 1 && l <= ART_MAX_LEVELS; ++l) tot += ct->w.tail[l];
+    atomicMax(&ct->c.rays_wave_max, tot);
+}
+
+// rate = s_H x_n n_H J_0 (Eq. e:photrate2); unpack fixed point; copy J.
+template <bool DET>
+__global__ void k_finalize(uint64_t N, const float* nH, const float* xn, double s_H, const float* J0,
+                           const unsigned long long* det, const Counters* ct, float* rate, float* force,
+                           float* J, int n_bins) {
+    const double inv = DET ? ct->c.inv_scale : 0.0;
+    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N;
+         c += (uint64_t)gridDim.x * blockDim.x) {
+        double j0;
+        if (DET) j0 = (double)(long long)det[c] * inv;
+        else j0 = (double)J0[c];
+        rate[c] = (float)(s_H * (double)xn[c] * (double)nH[c] * j0);
+        if (DET) {
+            force[c] = (float)((double)(long long)det[2 * N + c] * inv);
+            force[N + c] = (float)((double)(long long)det[3 * N + c] * inv);
+            force[2 * N + c] = (float)((double)(long long)det[4 * N + c] * inv);
+            if (J) {
+                J[c] = (float)j0;
+                if (n_bins > 1) J[N + c] = (float)((double)(long long)det[N + c] * inv);
+            }
+        } else if (J) {
+            J[c] = (float)j0;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Adjoint sweep of one level (children first: launched from the deepest level)
+// --------------------------------------------------------------------------
+
+
+// For every ray of the level: pass 1 recomputes its segments and sums its own
+// per-bin loss contributions T_b; G_b(start) = T_b + sum of the children's
+// G_b(start) is stored for the parent level.  Pass 2 walks the same segments
+// again and deposits dL/dkappa_b of each cell:
+//   [b = ionizing] a L_in dr^2 phi'(dtau) + beta L_in dr e^{-dtau} - dr G_b(after the segment)
+// with a = w s_H x_n n_H (the rate weight) and beta = v . n (the force weight):
+// every downstream contribution is proportional to e^{-tau}, so its derivative
+// with respect to this segment's opacity is -dr times its value.
+template <int NB, bool DET>
+__device__ inline void adjoint_ray(const AdjArgs& a, Counters* ct, int level, uint64_t slot, double gscale) {
+    const Geo& g = a.g;
+    const uint32_t N = a.N;
+    const uint32_t src = a.pool.src[slot];
+    const uint32_t pix = a.pool.pix[slot];
+    if (src >= a.n_src) return;
+    double tau0[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) tau0[b] = a.pool.tau[2 * slot + b];
+    Ray r;
+    ray_setup(g, a.src_pos, src, level, pix, r);
+    double Gend[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) Gend[b] = 0.0;
+    const uint32_t ch = a.pool.child[slot];
+    if (ch != kNoChild) {
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) Gend[b] += a.pool.G[2 * ((uint64_t)ch + k) + b];
+    }
+    double T[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) T[b] = 0.0;
+    if (source_inside(g, r.xs) && !r.starts_outside) {
+        // The gradient of a cell is a sum of terms of both signs (the explicit
+        // absorption terms against -dr G of everything downstream), so the
+        // per-segment arithmetic and the accumulation are FP64 here.
+        double lnom[NB];
+        const double inv_nray = 1.0 / (12.0 * ldexp(1.0, 2 * level));
+#pragma unroll
+        for (int b = 0; b < NB; ++b) lnom[b] = (double)a.src_lum[(uint64_t)src * NB + b] * inv_nray;
+        const double sH = g.s_H;
+        bool stuck = false;
+        // pass 1: the ray's own loss contributions T_b
+        double tau[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) tau[b] = tau0[b];
+        march<NB>(g, a.nH, a.xn, r, tau, &stuck,
+            [&](uint32_t c, double dr, const double (&dtau)[NB], const double (&tin)[NB]) {
+                const double wa = (double)a.w[c] * sH * (double)a.xn[c] * (double)a.nH[c];
+                const double beta = (double)a.v[c] * r.n[0] + (double)a.v[(uint64_t)N + c] * r.n[1] +
+                                    (double)a.v[2ull * N + c] * r.n[2];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const double x = dtau[b];
+                    const double Lin = lnom[b] * exp(-tin[b]);
+                    const double om = -expm1(-x);
+                    double own = beta * Lin * om;
+                    if (b == 0) own += wa * Lin * dr * absorb_phi(x, om);
+                    T[b] += own;
+                }
+            });
+        // pass 2: dL/dkappa_b of every crossed cell
+        double P[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            P[b] = 0.0;
+            tau[b] = tau0[b];
+        }
+        march<NB>(g, a.nH, a.xn, r, tau, &stuck,
+            [&](uint32_t c, double dr, const double (&dtau)[NB], const double (&tin)[NB]) {
+                const double wa = (double)a.w[c] * sH * (double)a.xn[c] * (double)a.nH[c];
+                const double beta = (double)a.v[c] * r.n[0] + (double)a.v[(uint64_t)N + c] * r.n[1] +
+                                    (double)a.v[2ull * N + c] * r.n[2];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const double x = dtau[b];
+                    const double Lin = lnom[b] * exp(-tin[b]);
+                    const double om = -expm1(-x);
+                    const double e = 1.0 - om;
+                    double own = beta * Lin * om;
+                    double dk = beta * Lin * dr * e;
+                    if (b == 0) {
+                        own += wa * Lin * dr * absorb_phi(x, om);
+                        dk += wa * Lin * dr * dr * absorb_dphi(x, e, om);
+                    }
+                    P[b] += own;
+                    const double after = (T[b] - P[b]) + Gend[b];
+                    const double d = dk - dr * after;
+                    if (DET) fx_add(&a.gdet[(uint64_t)b * N + c], d, gscale);
+                    else unsafeAtomicAdd(&a.gk[(uint64_t)b * N + c], d);
+                }
+            });
+        if (stuck) atomicOr(&ct->c.status, (uint32_t)kStStuck);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) a.pool.G[2 * slot + b] = T[b] + Gend[b];
+}
+
+template <int NB, bool DET>
+__global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
+    Counters* ct = a.ct;
+    if (ct->c.status & kStOverflow) return;
+    const uint64_t off = ct->w.off[level];
+    const uint32_t n_level =
+        (uint32_t)std::min<uint64_t>(ct->w.tail[level], a.pool.cap > off ? a.pool.cap - off : 0);
+    const double gscale = DET ? ct->c.gscale : 0.0;
+    for (;;) {
+        const uint32_t li = atomicAdd(&ct->w.adj_head[level], 1u);
+        if (__ballot(li < n_level) == 0ull) break;
+        if (li < n_level) adjoint_ray<NB, DET>(a, ct, level, off + li, gscale);
+    }
+}
+
+// g_nH = dL/dk0 (x_n s_H + s_d) + dL/dk1 s_d + w s_H x_n J0;  g_xn = dL/dk0 n_H s_H + w s_H n_H J0
+template <bool DET>
+__global__ void k_adj_finalize(uint64_t N, int n_bins, const float* nH, const float* xn, double s_H,
+                               double s_d, const float* w, const float* J0, const unsigned long long* det,
+                               const double* gk, const unsigned long long* gdet, const Counters* ct,
+                               float* g_nH, float* g_xn) {
+    const double inv = DET ? ct->c.inv_scale : 0.0;
+    const double ginv = DET ? ct->c.inv_gscale : 0.0;
+    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N;
+         c += (uint64_t)gridDim.x * blockDim.x) {
+        double j0, k0, k1 = 0.0;
+        if (DET) {
+            j0 = (double)(long long)det[c] * inv;
+            k0 = (double)(long long)gdet[c] * ginv;
+            if (n_bins > 1) k1 = (double)(long long)gdet[N + c] * ginv;
+        } else {
+            j0 = (double)J0[c];
+            k0 = gk[c];
+            if (n_bins > 1) k1 = gk[N + c];
+        }
+        const double x = (double)xn[c], n = (double)nH[c], ww = (double)w[c];
+        g_nH[c] = (float)(k0 * (x * s_H + s_d) + k1 * s_d + ww * s_H * x * j0);
+        g_xn[c] = (float)(k0 * n * s_H + ww * s_H * n * j0);
+    }
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// Host side
+// --------------------------------------------------------------------------
+
+struct art_ctx {
+    int nx, ny, nz;
+    uint64_t N;
+    art_params p;
+    art_options o;
+    hipStream_t stream;
+    int device;
+    int cu_count;
+    Geo geo;
+    Pool pool;
+    uint64_t per_src_bound;
+    int wave_max;
+    Counters* ct;
+    SrcStats st;
+    float* J0;
+    unsigned long long* det;
+    double* gk;
+    unsigned long long* gdet;
+    float* fscratch;
+    // tape of the last forward (valid only for a single-wave trace)
+    const void* tape_key[4];
+    int tape_nsrc;
+    bool tape_ok;
+    int last_nsrc, last_waves;
+    // timing
+    bool timing;
+    std::vector<hipEvent_t> ev;
+    int ev_used;
+    hipEvent_t ev_call0, ev_call1;
+};
+
+namespace {
+
+#define HIP_TRY(x)                                        \
+    do {                                                  \
+        hipError_t e_ = (x);                              \
+        if (e_ != hipSuccess) return ART_ERR_HIP;         \
+    } while (0)
+
+int fill_blocks(uint64_t n) {
+    uint64_t b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+template <class T>
+int zero(art_ctx* c, T* p, uint64_t n);
+template <>
+int zero<float>(art_ctx* c, float* p, uint64_t n) {
+    if (!n) return ART_OK;
+    hipLaunchKernelGGL(k_fill_f32, dim3(fill_blocks(n)), dim3(256), 0, c->stream, p, n);
+    HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+template <>
+int zero<double>(art_ctx* c, double* p, uint64_t n) {
+    if (!n) return ART_OK;
+    hipLaunchKernelGGL(k_fill_f64, dim3(fill_blocks(n)), dim3(256), 0, c->stream, p, n);
+    HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+template <>
+int zero<unsigned long long>(art_ctx* c, unsigned long long* p, uint64_t n) {
+    if (!n) return ART_OK;
+    hipLaunchKernelGGL(k_fill_u64, dim3(fill_blocks(n)), dim3(256), 0, c->stream, p, n);
+    HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+template <>
+int zero<uint32_t>(art_ctx* c, uint32_t* p, uint64_t n) {
+    if (!n) return ART_OK;
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(n)), dim3(256), 0, c->stream, p, n, 0u);
+    HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+
+double r_max_host(double phi_c, int level) { return sqrt(3.0 / (M_PI * phi_c)) * ldexp(1.0, level); }
+
+// Upper bound on the rays one source can create at each level, from geometry
+// alone: level-l rays exist only where r_max(l-1) is inside the box, and the
+// parents that split at r_max(l-1) have pixel centres on the part of that
+// sphere inside the box, whose area is at most the box surface S; each such
+// pixel covers 1/m_ray of area there, so at most ~4 m_ray S children (a factor
+// 2 of margin for pixels straddling the boundary).
+uint64_t rays_bound_per_source(int nx, int ny, int nz, const art_params& p) {
+    const double diag = sqrt((double)nx * nx + (double)ny * ny + (double)nz * nz);
+    const double S = 2.0 * ((double)nx * ny + (double)ny * nz + (double)nz * nx);
+    uint64_t tot = 0;
+    for (int l = p.level0; l <= p.level_max; ++l) {
+        const uint64_t all = 12ull << (2 * l);
+        if (l == p.level0) {
+            tot += all;
+            continue;
+        }
+        if (r_max_host(p.phi_c, l - 1) >= diag) break;
+        const double geo = 4.0 * (2.0 * p.phi_c * S + 1024.0);
+        tot += (uint64_t)std::min((double)all, geo);
+    }
+    return tot;
+}
+
+int check_params(const art_params* p) {
+    if (!p) return ART_ERR_INVALID_ARG;
+    if (p->level0 < 0 || p->level_max < p->level0 || p->level_max >= ART_MAX_LEVELS) return ART_ERR_INVALID_ARG;
+    if (p->level_max > 14) return ART_ERR_INVALID_ARG;  // 12*4^l pixel ids must fit 32 bits
+    if (p->n_bins < 1 || p->n_bins > ART_MAX_BINS) return ART_ERR_INVALID_ARG;
+    if (!(p->phi_c > 0.0) || !(p->tau_term > 0.0) || !(p->s_H >= 0.0) || !(p->s_d >= 0.0))
+        return ART_ERR_INVALID_ARG;
+    if (p->deposit_mode != ART_DEPOSIT_ATOMIC && p->deposit_mode != ART_DEPOSIT_DETERMINISTIC)
+        return ART_ERR_INVALID_ARG;
+    for (int i = 0; i < 9; ++i)
+        if (!isfinite(p->rot[i])) return ART_ERR_INVALID_ARG;
+    return ART_OK;
+}
+
+void free_all(art_ctx* c) {
+    (void)hipFree(c->pool.src);
+    (void)hipFree(c->pool.pix);
+    (void)hipFree(c->pool.tau);
+    (void)hipFree(c->pool.child);
+    (void)hipFree(c->pool.G);
+    (void)hipFree(c->ct);
+    (void)hipFree(c->st.created);
+    (void)hipFree(c->st.split);
+    (void)hipFree(c->st.exited);
+    (void)hipFree(c->st.term);
+    (void)hipFree(c->st.escaped);
+    (void)hipFree(c->st.residual);
+    (void)hipFree(c->st.segments);
+    (void)hipFree(c->J0);
+    (void)hipFree(c->det);
+    (void)hipFree(c->gk);
+    (void)hipFree(c->gdet);
+    (void)hipFree(c->fscratch);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->ev_call0) (void)hipEventDestroy(c->ev_call0);
+    if (c->ev_call1) (void)hipEventDestroy(c->ev_call1);
+}
+
+template <class T>
+bool dmalloc(T** p, uint64_t n) {
+    *p = nullptr;
+    if (n == 0) return true;
+    return hipMalloc((void**)p, n * sizeof(T)) == hipSuccess;
+}
+
+SweepArgs sweep_args(art_ctx* c, const float* nH, const float* xn, const double* pos, const float* lum,
+                     float* force, float* J, int n_src) {
+    SweepArgs a;
+    a.g = c->geo;
+    a.nH = nH;
+    a.xn = xn;
+    a.src_pos = pos;
+    a.src_lum = lum;
+    a.pool = c->pool;
+    a.ct = c->ct;
+    a.st = c->st;
+    a.J0 = c->J0;
+    a.J1 = (J && c->p.n_bins > 1) ? J + c->N : nullptr;
+    a.F = force;
+    a.det = c->det;
+    a.N = (uint32_t)c->N;
+    a.n_src = (uint32_t)n_src;
+    return a;
+}
+
+int launch_sweep(art_ctx* c, const SweepArgs& a, int level, bool full) {
+    const dim3 grid((unsigned)(c->cu_count * c->o.blocks_per_cu)), block((unsigned)c->o.block_size);
+    const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
+    const int nb = c->p.n_bins;
+    const bool tm = c->timing && c->ev_used + 2 <= (int)c->ev.size();
+    if (tm) HIP_TRY(hipEventRecord(c->ev[c->ev_used], c->stream));
+#define SWEEP(NB, DET, FULL) hipLaunchKernelGGL((k_sweep<NB, DET, FULL>), grid, block, 0, c->stream, a, level)
+    if (nb == 1) {
+        if (det) { if (full) SWEEP(1, true, true); else SWEEP(1, true, false); }
+        else { if (full) SWEEP(1, false, true); else SWEEP(1, false, false); }
+    } else {
+        if (det) { if (full) SWEEP(2, true, true); else SWEEP(2, true, false); }
+        else { if (full) SWEEP(2, false, true); else SWEEP(2, false, false); }
+    }
+#undef SWEEP
+    HIP_TRY(hipGetLastError());
+    if (tm) {
+        HIP_TRY(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+        c->ev_used += 2;
+    }
+    return ART_OK;
+}
+
+int launch_adjoint(art_ctx* c, const AdjArgs& a, int level) {
+    const dim3 grid((unsigned)(c->cu_count * c->o.blocks_per_cu)), block((unsigned)c->o.block_size);
+    const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
+    if (c->p.n_bins == 1) {
+        if (det) hipLaunchKernelGGL((k_adjoint<1, true>), grid, block, 0, c->stream, a, level);
+        else hipLaunchKernelGGL((k_adjoint<1, false>), grid, block, 0, c->stream, a, level);
+    } else {
+        if (det) hipLaunchKernelGGL((k_adjoint<2, true>), grid, block, 0, c->stream, a, level);
+        else hipLaunchKernelGGL((k_adjoint<2, false>), grid, block, 0, c->stream, a, level);
+    }
+    HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+
+int seed_wave(art_ctx* c, int s0, int n_wave) {
+    const uint64_t n = (uint64_t)(12ull << (2 * c->p.level0)) * (uint64_t)n_wave;
+    hipLaunchKernelGGL(k_seed, dim3(fill_blocks(n)), dim3(256), 0, c->stream, c->pool, c->ct, c->p.level0, s0,
+                       n_wave, c->p.n_bins, c->pool.child ? 1 : 0);
+    HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+
+// Sweep every level of the current wave, l0 first.
+int sweep_wave(art_ctx* c, const SweepArgs& a, bool full) {
+    for (int l = c->p.level0; l <= c->p.level_max; ++l) {
+        int rc = launch_sweep(c, a, l, full);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_end_wave, dim3(1), dim3(64), 0, c->stream, c->ct, c->p.level0, c->p.level_max);
+    HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+
+int begin_call(art_ctx* c, const float* lum, int n_src) {
+    hipLaunchKernelGGL(k_begin_call, dim3(1), dim3(256), 0, c->stream, c->ct, lum, n_src * c->p.n_bins);
+    HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* art_strerror(int code) {
+    switch (code) {
+        case ART_OK: return "ok";
+        case ART_ERR_INVALID_ARG: return "invalid argument";
+        case ART_ERR_HIP: return "HIP runtime error";
+        case ART_ERR_OUT_OF_MEMORY: return "out of device memory for the workspace";
+        case ART_ERR_QUEUE_OVERFLOW: return "ray pool overflow (increase pool_rays)";
+        case ART_ERR_SOURCE_OUTSIDE: return "a source lies outside the domain";
+        case ART_ERR_DESTROY_COUNT: return "destroy counter does not match N_src*12*4^level_max";
+        case ART_ERR_NO_FORWARD: return "context was created without adjoint support";
+        default: return "unknown error";
+    }
+}
+
+int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, const art_options* opts,
+               void* stream) {
+    if (!out) return ART_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (nx <= 0 || ny <= 0 || nz <= 0) return ART_ERR_INVALID_ARG;
+    const uint64_t N = (uint64_t)nx * ny * nz;
+    if (N >= (1ull << 32)) return ART_ERR_INVALID_ARG;
+    int rc = check_params(params);
+    if (rc) return rc;
+    art_options o;
+    memset(&o, 0, sizeof o);
+    if (opts) o = *opts;
+    if (o.max_sources <= 0) return ART_ERR_INVALID_ARG;
+    if (o.block_size == 0) o.block_size = 256;
+    if (o.blocks_per_cu == 0) o.blocks_per_cu = 4;
+    if (o.block_size < 64 || o.block_size > 256 || (o.block_size % 64) || o.blocks_per_cu < 1 ||
+        o.blocks_per_cu > 64)
+        return ART_ERR_INVALID_ARG;
+    if (!(o.pool_mem_fraction > 0.0 && o.pool_mem_fraction <= 0.95)) o.pool_mem_fraction = 0.5;
+
+    art_ctx* c = new (std::nothrow) art_ctx();
+    if (!c) return ART_ERR_OUT_OF_MEMORY;
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->N = N;
+    c->p = *params;
+    c->o = o;
+    c->stream = (hipStream_t)stream;
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
+        delete c;
+        return ART_ERR_HIP;
+    }
+    Geo& g = c->geo;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.level0 = params->level0;
+    g.level_max = params->level_max;
+    g.n_bins = params->n_bins;
+    g.tau_term = params->tau_term;
+    g.s_H = params->s_H;
+    g.s_d = params->s_d;
+    for (int i = 0; i < 9; ++i) g.rot[i] = params->rot[i];
+    for (int l = 0; l < ART_MAX_LEVELS; ++l) g.rmax[l] = r_max_host(params->phi_c, l);
+
+    // ray pool
+    c->per_src_bound = rays_bound_per_source(nx, ny, nz, *params);
+    const uint64_t bytes_per_ray = 4 + 4 + 16 + (o.enable_adjoint ? 4 + 16 : 0);
+    uint64_t cap = (uint64_t)o.pool_rays;
+    if (cap == 0) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            delete c;
+            return ART_ERR_HIP;
+        }
+        const uint64_t want = c->per_src_bound * (uint64_t)o.max_sources;
+        const uint64_t fits = (uint64_t)((double)free_b * o.pool_mem_fraction) / bytes_per_ray;
+        cap = std::min(want, fits);
+    }
+    cap = std::min<uint64_t>(cap, 0xfffffff0ull);
+    const uint64_t seeds = 12ull << (2 * params->level0);
+    if (cap < seeds) {
+        delete c;
+        return ART_ERR_OUT_OF_MEMORY;
+    }
+    c->pool.cap = cap;
+    uint64_t wave = cap / std::max<uint64_t>(c->per_src_bound, 1);
+    if (wave < 1) wave = 1;  // a single source may still fit (the bound is loose)
+    c->wave_max = (int)std::min<uint64_t>(wave, (uint64_t)o.max_sources);
+
+    const bool det = params->deposit_mode == ART_DEPOSIT_DETERMINISTIC;
+    const uint64_t ms = (uint64_t)o.max_sources;
+    bool ok = dmalloc(&c->pool.src, cap) && dmalloc(&c->pool.pix, cap) && dmalloc(&c->pool.tau, 2 * cap) &&
+              dmalloc(&c->ct, 1) && dmalloc(&c->st.created, ms * ART_MAX_LEVELS) &&
+              dmalloc(&c->st.split, ms * ART_MAX_LEVELS) && dmalloc(&c->st.exited, ms * ART_MAX_LEVELS) &&
+              dmalloc(&c->st.term, ms * ART_MAX_LEVELS) && dmalloc(&c->st.escaped, ms * 2) &&
+              dmalloc(&c->st.residual, ms * 2) && dmalloc(&c->st.segments, ms) && dmalloc(&c->fscratch, 64);
+    if (ok && o.enable_adjoint)
+        ok = dmalloc(&c->pool.child, cap) && dmalloc(&c->pool.G, 2 * cap);
+    if (ok) ok = det ? dmalloc(&c->det, 5 * N) : dmalloc(&c->J0, N);
+    if (ok && o.enable_adjoint) ok = det ? dmalloc(&c->gdet, 2 * N) : dmalloc(&c->gk, 2 * N);
+    if (ok) {
+        c->ev.resize(2 * (ART_MAX_LEVELS + 1) * 64);
+        for (auto& e : c->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+        ok = ok && hipEventCreate(&c->ev_call0) == hipSuccess && hipEventCreate(&c->ev_call1) == hipSuccess;
+    }
+    if (!ok) {
+        free_all(c);
+        delete c;
+        (void)hipGetLastError();
+        return ART_ERR_OUT_OF_MEMORY;
+    }
+    *out = c;
+    return ART_OK;
+}
+
+int art_set_stream(art_ctx* c, void* stream) {
+    if (!c) return ART_ERR_INVALID_ARG;
+    c->stream = (hipStream_t)stream;
+    return ART_OK;
+}
+
+int art_trace(art_ctx* c, const float* n_H, const float* x_n, const double* src_pos, const float* src_lum,
+              int n_src, float* rate, float* force, float* J) {
+    if (!c || !n_H || !x_n || !rate || !force) return ART_ERR_INVALID_ARG;
+    if (n_src < 0 || n_src > c->o.max_sources) return ART_ERR_INVALID_ARG;
+    if (n_src > 0 && (!src_pos || !src_lum)) return ART_ERR_INVALID_ARG;
+    const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
+    const uint64_t N = c->N;
+    const uint64_t ms = (uint64_t)c->o.max_sources;
+    c->ev_used = 0;
+    c->tape_ok = false;
+    if (c->timing) HIP_TRY(hipEventRecord(c->ev_call0, c->stream));
+    int rc;
+    if ((rc = begin_call(c, src_lum, n_src))) return rc;
+    if ((rc = zero(c, force, 3 * N))) return rc;
+    if (det) {
+        if ((rc = zero(c, c->det, 5 * N))) return rc;
+    } else {
+        if ((rc = zero(c, c->J0, N))) return rc;
+        if (J && c->p.n_bins > 1 && (rc = zero(c, J + N, N))) return rc;
+    }
+    if ((rc = zero(c, c->st.created, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.split, ms * ART_MAX_LEVELS)) ||
+        (rc = zero(c, c->st.exited, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.term, ms * ART_MAX_LEVELS)) ||
+        (rc = zero(c, c->st.escaped, ms * 2)) || (rc = zero(c, c->st.residual, ms * 2)) ||
+        (rc = zero(c, c->st.segments, ms)))
+        return rc;
+    const SweepArgs a = sweep_args(c, n_H, x_n, src_pos, src_lum, force, J, n_src);
+    int waves = 0;
+    for (int s0 = 0; s0 < n_src; s0 += c->wave_max) {
+        const int nw = std::min(c->wave_max, n_src - s0);
+        if ((rc = seed_wave(c, s0, nw))) return rc;
+        if ((rc = sweep_wave(c, a, true))) return rc;
+        ++waves;
+    }
+    const dim3 fg(fill_blocks(N)), fb(256);
+    if (det)
+        hipLaunchKernelGGL((k_finalize<true>), fg, fb, 0, c->stream, N, n_H, x_n, c->p.s_H, c->J0, c->det, c->ct,
+                           rate, force, J, c->p.n_bins);
+    else
+        hipLaunchKernelGGL((k_finalize<false>), fg, fb, 0, c->stream, N, n_H, x_n, c->p.s_H, c->J0, c->det,
+                           c->ct, rate, force, J, c->p.n_bins);
+    HIP_TRY(hipGetLastError());
+    if (c->timing) HIP_TRY(hipEventRecord(c->ev_call1, c->stream));
+    c->last_nsrc = n_src;
+    c->last_waves = waves;
+    if (c->o.enable_adjoint && waves == 1) {
+        c->tape_key[0] = n_H;
+        c->tape_key[1] = x_n;
+        c->tape_key[2] = src_pos;
+        c->tape_key[3] = src_lum;
+        c->tape_nsrc = n_src;
+        c->tape_ok = true;
+    }
+    return ART_OK;
+}
+
+int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const double* src_pos, const float* src_lum,
+                      int n_src, const float* g_rate, const float* g_force, float* g_nH, float* g_xn) {
+    if (!c || !n_H || !x_n || !g_rate || !g_force || !g_nH || !g_xn) return ART_ERR_INVALID_ARG;
+    if (!c->o.enable_adjoint) return ART_ERR_NO_FORWARD;
+    if (n_src < 0 || n_src > c->o.max_sources) return ART_ERR_INVALID_ARG;
+    if (n_src > 0 && (!src_pos || !src_lum)) return ART_ERR_INVALID_ARG;
+    const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
+    const uint64_t N = c->N;
+    int rc;
+    const bool reuse = c->tape_ok && c->tape_key[0] == n_H && c->tape_key[1] == x_n &&
+                       c->tape_key[2] == src_pos && c->tape_key[3] == src_lum && c->tape_nsrc == n_src;
+    if (det) {
+        if ((rc = zero(c, (uint32_t*)c->fscratch, 1))) return rc;
+        hipLaunchKernelGGL(k_adj_scale, dim3(fill_blocks(N) < 1024 ? fill_blocks(N) : 1024), dim3(256), 0,
+                           c->stream, c->ct, g_rate, g_force, N, src_lum, n_src * c->p.n_bins, c->fscratch);
+        HIP_TRY(hipGetLastError());
+        double sHmax = c->p.s_H + c->p.s_d;
+        hipLaunchKernelGGL(k_adj_scale_final, dim3(1), dim3(64), 0, c->stream, c->ct, src_lum, n_src * c->p.n_bins,
+                           c->fscratch, sHmax);
+        HIP_TRY(hipGetLastError());
+        if ((rc = zero(c, c->gdet, 2 * N))) return rc;
+    } else {
+        if ((rc = zero(c, c->gk, 2 * N))) return rc;
+    }
+    AdjArgs aa;
+    aa.g = c->geo;
+    aa.nH = n_H;
+    aa.xn = x_n;
+    aa.src_pos = src_pos;
+    aa.src_lum = src_lum;
+    aa.w = g_rate;
+    aa.v = g_force;
+    aa.pool = c->pool;
+    aa.ct = c->ct;
+    aa.gk = c->gk;
+    aa.gdet = c->gdet;
+    aa.N = (uint32_t)N;
+    aa.n_src = (uint32_t)n_src;
+    if (reuse) {
+        for (int l = c->p.level_max; l >= c->p.level0; --l)
+            if ((rc = launch_adjoint(c, aa, l))) return rc;
+    } else {
+        // rebuild the tree wave by wave (tau recomputed, no segment storage),
+        // with J0 deposited for the explicit rate term
+        if ((rc = begin_call(c, src_lum, n_src))) return rc;
+        if (det) {
+            if ((rc = zero(c, c->det, N))) return rc;
+        } else if ((rc = zero(c, c->J0, N))) {
+            return rc;
+        }
+        const uint64_t ms = (uint64_t)c->o.max_sources;
+        if ((rc = zero(c, c->st.created, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.split, ms * ART_MAX_LEVELS)) ||
+            (rc = zero(c, c->st.exited, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.term, ms * ART_MAX_LEVELS)) ||
+            (rc = zero(c, c->st.escaped, ms * 2)) || (rc = zero(c, c->st.residual, ms * 2)) ||
+            (rc = zero(c, c->st.segments, ms)))
+            return rc;
+        const SweepArgs a = sweep_args(c, n_H, x_n, src_pos, src_lum, nullptr, nullptr, n_src);
+        for (int s0 = 0; s0 < n_src; s0 += c->wave_max) {
+            const int nw = std::min(c->wave_max, n_src - s0);
+            if ((rc = seed_wave(c, s0, nw))) return rc;
+            if ((rc = sweep_wave(c, a, false))) return rc;
+            for (int l = c->p.level_max; l >= c->p.level0; --l)
+                if ((rc = launch_adjoint(c, aa, l))) return rc;
+        }
+        c->last_nsrc = n_src;
+        c->last_waves = (n_src + c->wave_max - 1) / c->wave_max;
+    }
+    const dim3 fg(fill_blocks(N)), fb(256);
+    if (det)
+        hipLaunchKernelGGL((k_adj_finalize<true>), fg, fb, 0, c->stream, N, c->p.n_bins, n_H, x_n, c->p.s_H,
+                           c->p.s_d, g_rate, c->J0, c->det, c->gk, c->gdet, c->ct, g_nH, g_xn);
+    else
+        hipLaunchKernelGGL((k_adj_finalize<false>), fg, fb, 0, c->stream, N, c->p.n_bins, n_H, x_n, c->p.s_H,
+                           c->p.s_d, g_rate, c->J0, c->det, c->gk, c->gdet, c->ct, g_nH, g_xn);
+    HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+
+static int status_code(const Counters& h, uint64_t expected) {
+    if (h.c.status & kStOverflow) return ART_ERR_QUEUE_OVERFLOW;
+    if (h.c.status & kStOutside) return ART_ERR_SOURCE_OUTSIDE;
+    if (h.c.status & kStStuck) return ART_ERR_INVALID_ARG;
+    if (h.c.destroy != expected) return ART_ERR_DESTROY_COUNT;
+    return ART_OK;
+}
+
+static uint64_t destroy_expected(const art_ctx* c, int n_src) {
+    return (uint64_t)n_src * (12ull << (2 * c->p.level_max));
+}
+
+int art_sync(art_ctx* c) {
+    if (!c) return ART_ERR_INVALID_ARG;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    Counters h;
+    HIP_TRY(hipMemcpy(&h, c->ct, sizeof h, hipMemcpyDeviceToHost));
+    return status_code(h, destroy_expected(c, c->last_nsrc));
+}
+
+int art_get_stats(art_ctx* c, art_stats* out, int ns, uint32_t* created, uint32_t* split, uint32_t* exited,
+                  uint32_t* terminated, double* escaped, double* residual, uint64_t* segments) {
+    if (!c || !out) return ART_ERR_INVALID_ARG;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    Counters h;
+    HIP_TRY(hipMemcpy(&h, c->ct, sizeof h, hipMemcpyDeviceToHost));
+    memset(out, 0, sizeof *out);
+    out->n_src = c->last_nsrc;
+    out->n_waves = c->last_waves;
+    out->segments = h.c.segments;
+    out->destroy = h.c.destroy;
+    out->destroy_expected = destroy_expected(c, c->last_nsrc);
+    out->rays_max_wave = h.c.rays_wave_max;
+    out->status = status_code(h, out->destroy_expected);
+    const int n_all = c->last_nsrc;
+    if (n_all > 0) {
+        std::vector<uint32_t> buf((size_t)n_all * ART_MAX_LEVELS);
+        uint32_t* dsrc[4] = {c->st.created, c->st.split, c->st.exited, c->st.term};
+        uint32_t* hdst[4] = {created, split, exited, terminated};
+        uint64_t* tot[4] = {out->created, out->split, out->exited, out->terminated};
+        for (int k = 0; k < 4; ++k) {
+            HIP_TRY(hipMemcpy(buf.data(), dsrc[k], buf.size() * 4, hipMemcpyDeviceToHost));
+            for (int s = 0; s < n_all; ++s)
+                for (int l = 0; l < ART_MAX_LEVELS; ++l) tot[k][l] += buf[(size_t)s * ART_MAX_LEVELS + l];
+            if (hdst[k] && ns > 0)
+                memcpy(hdst[k], buf.data(), (size_t)std::min(ns, n_all) * ART_MAX_LEVELS * 4);
+        }
+        const int m = std::min(ns, n_all);
+        if (m > 0) {
+            if (escaped) HIP_TRY(hipMemcpy(escaped, c->st.escaped, (size_t)m * 2 * 8, hipMemcpyDeviceToHost));
+            if (residual) HIP_TRY(hipMemcpy(residual, c->st.residual, (size_t)m * 2 * 8, hipMemcpyDeviceToHost));
+            if (segments) HIP_TRY(hipMemcpy(segments, c->st.segments, (size_t)m * 8, hipMemcpyDeviceToHost));
+        }
+    }
+    return ART_OK;
+}
+
+int art_set_timing(art_ctx* c, int enable) {
+    if (!c) return ART_ERR_INVALID_ARG;
+    c->timing = enable != 0;
+    return ART_OK;
+}
+
+int art_get_timing(art_ctx* c, float* sweep_ms_total, int* sweep_launches, float* total_ms) {
+    if (!c) return ART_ERR_INVALID_ARG;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    float tot = 0.0f;
+    for (int i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+        tot += ms;
+    }
+    if (sweep_ms_total) *sweep_ms_total = tot;
+    if (sweep_launches) *sweep_launches = c->ev_used / 2;
+    if (total_ms) {
+        float ms = 0.0f;
+        if (c->timing && hipEventElapsedTime(&ms, c->ev_call0, c->ev_call1) != hipSuccess) ms = 0.0f;
+        *total_ms = ms;
+    }
+    return ART_OK;
+}
+
+int art_autotune(art_ctx* c, const float* n_H, const float* x_n, const double* src_pos, const float* src_lum,
+                 int n_src, float* rate, float* force, int* best_block, int* best_bpc, float* best_ms) {
+    if (!c) return ART_ERR_INVALID_ARG;
+    static const int cand[][2] = {{64, 8}, {64, 16}, {128, 4}, {128, 8}, {256, 2}, {256, 4}, {256, 8}};
+    const art_options keep = c->o;
+    const bool keep_timing = c->timing;
+    c->timing = true;
+    float best = 1e30f;
+    int bb = keep.block_size, bp = keep.blocks_per_cu;
+    for (const auto& cd : cand) {
+        c->o.block_size = cd[0];
+        c->o.blocks_per_cu = cd[1];
+        float ms_best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            int rc = art_trace(c, n_H, x_n, src_pos, src_lum, n_src, rate, force, nullptr);
+            if (rc) {
+                c->o = keep;
+                c->timing = keep_timing;
+                return rc;
+            }
+            float tot = 0.0f;
+            rc = art_get_timing(c, nullptr, nullptr, &tot);
+            if (rc) {
+                c->o = keep;
+                c->timing = keep_timing;
+                return rc;
+            }
+            if (rep > 0) ms_best = std::min(ms_best, tot);
+        }
+        if (ms_best < best) {
+            best = ms_best;
+            bb = cd[0];
+            bp = cd[1];
+        }
+    }
+    c->o.block_size = bb;
+    c->o.blocks_per_cu = bp;
+    c->timing = keep_timing;
+    if (best_block) *best_block = bb;
+    if (best_bpc) *best_bpc = bp;
+    if (best_ms) *best_ms = best;
+    return art_sync(c);
+}
+
+void art_destroy(art_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+}  // extern "C"

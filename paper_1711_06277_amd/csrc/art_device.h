@@ -1,0 +1,263 @@
+// art_device.h -- device-side building blocks of the ART sweep for gfx950:
+// HEALPix nested ray directions, the per-ray geometry of Sec. 2.1 (split
+// radius, domain exit), and the cell-by-cell march (Amanatides-Woo traversal)
+// with optical-depth bookkeeping.
+//
+// Precision: ray geometry, the running optical depth tau and every decision
+// (split / exit / termination) are FP64, so the ray tree does not depend on the
+// FP32 rounding of the deposits.  Compiled with -ffp-contract=off.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/art.h"
+
+namespace art {
+
+constexpr int kWave = 64;
+constexpr uint32_t kNoChild = 0xffffffffu;
+
+// How a ray's march ended (Sec. 2.1): at the split radius, at the domain
+// boundary, or because every bin became optically thick (tau > tau_term).
+enum End : int { kExit = 0, kSplit = 1, kTerm = 2 };
+
+// Device status bits (first error wins when reported).
+enum Status : uint32_t {
+    kStOverflow = 1u,
+    kStOutside = 2u,
+    kStStuck = 4u,
+};
+
+// Per-call constants of the sweep, passed by value to every kernel.
+struct Geo {
+    int nx, ny, nz;
+    int level0, level_max, n_bins;
+    double tau_term, s_H, s_d;
+    double rot[9];
+    double rmax[ART_MAX_LEVELS];  // r_max(l) = sqrt(3/(pi m_ray)) 2^l
+};
+
+// ---------------------------------------------------------------------------
+// HEALPix nested scheme (Gorski et al. 2005).
+// ---------------------------------------------------------------------------
+
+// Gather the even-position bits of v into the low half (inverse of the
+// Z-order interleave used by the nested numbering inside a base face).
+__device__ __forceinline__ uint32_t gather_even_bits(uint64_t v) {
+    v &= 0x5555555555555555ull;
+    v = (v | (v >> 1)) & 0x3333333333333333ull;
+    v = (v | (v >> 2)) & 0x0f0f0f0f0f0f0f0full;
+    v = (v | (v >> 4)) & 0x00ff00ff00ff00ffull;
+    v = (v | (v >> 8)) & 0x0000ffff0000ffffull;
+    v = (v | (v >> 16)) & 0x00000000ffffffffull;
+    return (uint32_t)v;
+}
+
+// Unit vector of the centre of nested pixel `pix` at nside = 2^level, before
+// the user rotation.  The 12 base faces sit in three rows of four; inside a
+// face the pixel's (px, py) come from the Z-order index.  The ring counted from
+// the north pole is (row + 2) nside - px - py - 1; rings above nside and below
+// 3 nside are polar-cap rings with 4*ring pixels, the others hold 4 nside.
+__device__ inline void healpix_nest_dir(int level, uint32_t pix, double v[3]) {
+    const int ns = 1 << level;
+    const uint32_t face = pix >> (2 * level);
+    const uint32_t in_face = pix & ((1u << (2 * level)) - 1u);
+    const int px = (int)gather_even_bits(in_face);
+    const int py = (int)gather_even_bits((uint64_t)in_face >> 1);
+    const int row = (int)(face >> 2);
+    const int col = (int)(face & 3u);
+    const int ring = (row + 2) * ns - px - py - 1;
+    double z, sin_theta;
+    int ring_q;       // pixels in the ring / 4
+    int half_shift;   // 1 if the ring's first pixel centre is at phi = 0
+    const double inv3n2 = 1.0 / (3.0 * (double)ns * (double)ns);
+    if (ring < ns) {
+        ring_q = ring;
+        const double t = (double)ring * (double)ring * inv3n2;  // 1 - z
+        z = 1.0 - t;
+        sin_theta = sqrt(t * (2.0 - t));
+        half_shift = 0;
+    } else if (ring > 3 * ns) {
+        ring_q = 4 * ns - ring;
+        const double t = (double)ring_q * (double)ring_q * inv3n2;  // 1 + z
+        z = t - 1.0;
+        sin_theta = sqrt(t * (2.0 - t));
+        half_shift = 0;
+    } else {
+        ring_q = ns;
+        z = (double)(2 * ns - ring) * (2.0 / (3.0 * (double)ns));
+        sin_theta = sqrt((1.0 - z) * (1.0 + z));
+        half_shift = (ring - ns) & 1;
+    }
+    // face column in units of half the in-ring spacing: odd for the polar rows
+    const int face_col = 2 * col + ((row == 1) ? 0 : 1);
+    int jp = (face_col * ring_q + px - py + 1 + half_shift) >> 1;
+    if (jp > 4 * ring_q) jp -= 4 * ring_q;
+    if (jp < 1) jp += 4 * ring_q;
+    const double phi = ((double)jp - 0.5 * (double)(1 + half_shift)) * (M_PI * 0.5 / (double)ring_q);
+    double s, c;
+    sincos(phi, &s, &c);
+    v[0] = sin_theta * c;
+    v[1] = sin_theta * s;
+    v[2] = z;
+}
+
+// ---------------------------------------------------------------------------
+// Per-ray geometry and the march
+// ---------------------------------------------------------------------------
+
+struct Ray {
+    double xs[3];     // source position
+    double n[3];      // unit direction (rotated)
+    double inv[3];    // 1/n (unused where n == 0)
+    double r_a;       // start radius: 0 at level0, r_max(l-1) otherwise
+    double r_end;     // r_split if the ray can split before leaving, else d_exit
+    bool can_split;   // r_max(l) < d_exit (a tie exits)
+    bool starts_outside;  // r_a >= d_exit: created outside the domain, no segment
+};
+
+__device__ inline void ray_setup(const Geo& g, const double* __restrict__ src_pos, uint32_t src,
+                                 int level, uint32_t pix, Ray& r) {
+    double v[3];
+    healpix_nest_dir(level, pix, v);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.xs[a] = src_pos[3 * src + a];
+        r.n[a] = g.rot[3 * a + 0] * v[0] + g.rot[3 * a + 1] * v[1] + g.rot[3 * a + 2] * v[2];
+        r.inv[a] = 1.0 / r.n[a];
+    }
+    const double hi[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
+    double d_exit = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double t = INFINITY;
+        if (r.n[a] > 0.0) t = (hi[a] - r.xs[a]) * r.inv[a];
+        else if (r.n[a] < 0.0) t = (0.0 - r.xs[a]) * r.inv[a];
+        d_exit = fmin(d_exit, t);
+    }
+    r.r_a = (level == g.level0) ? 0.0 : g.rmax[level - 1];
+    const double r_split = (level < g.level_max) ? g.rmax[level] : INFINITY;
+    r.can_split = r_split < d_exit;
+    r.r_end = r.can_split ? r_split : d_exit;
+    r.starts_outside = !(r.r_a < d_exit);
+}
+
+__device__ __forceinline__ bool source_inside(const Geo& g, const double* xs) {
+    return xs[0] >= 0.0 && xs[0] < (double)g.nx && xs[1] >= 0.0 && xs[1] < (double)g.ny &&
+           xs[2] >= 0.0 && xs[2] < (double)g.nz;
+}
+
+// March one ray from r_a to r_end, cell by cell.  For every segment of positive
+// length calls visit(cell, dr, dtau[], tau_in[]) with the optical depth of each
+// bin over the segment and from the source to the segment's entry; then
+// tau[] += dtau[].  Returns kTerm as soon as tau_b > tau_term in every bin,
+// kSplit / kExit on reaching r_end.  *stuck is set if the traversal failed to
+// advance (non-finite input); the step count is bounded by the grid size, so
+// every lane terminates.
+template <int NB, class Visit>
+__device__ inline int march(const Geo& g, const float* __restrict__ nH, const float* __restrict__ xn,
+                            const Ray& r, double (&tau)[NB], bool* stuck, Visit&& visit) {
+    int cell[3];
+    double tnext[3];
+    const int dims[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double p = r.xs[a] + r.r_a * r.n[a];
+        int c = (int)floor(p);
+        c = c < 0 ? 0 : (c > dims[a] - 1 ? dims[a] - 1 : c);
+        cell[a] = c;
+        if (r.n[a] > 0.0) tnext[a] = ((double)(c + 1) - r.xs[a]) * r.inv[a];
+        else if (r.n[a] < 0.0) tnext[a] = ((double)c - r.xs[a]) * r.inv[a];
+        else tnext[a] = INFINITY;
+    }
+    double rr = r.r_a;
+    const int max_steps = g.nx + g.ny + g.nz + 8;
+    for (int it = 0; it < max_steps; ++it) {
+        double rb = fmin(fmin(tnext[0], tnext[1]), tnext[2]);
+        const bool ends = !(rb < r.r_end);
+        if (ends) rb = r.r_end;
+        const double dr = rb - rr;
+        if (dr > 0.0) {
+            const uint32_t c = ((uint32_t)cell[2] * (uint32_t)g.ny + (uint32_t)cell[1]) * (uint32_t)g.nx +
+                               (uint32_t)cell[0];
+            const double dnH = (double)nH[c];
+            double kap[NB];
+            kap[0] = dnH * ((double)xn[c] * g.s_H + g.s_d);
+            if (NB > 1) kap[NB - 1] = dnH * g.s_d;
+            double dtau[NB];
+            bool thick = true;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) dtau[b] = kap[b] * dr;
+            visit(c, dr, dtau, tau);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                tau[b] += dtau[b];
+                thick = thick && (tau[b] > g.tau_term);
+            }
+            if (thick) return kTerm;
+            rr = rb;
+        }
+        if (ends) return r.can_split ? kSplit : kExit;
+        bool moved = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (tnext[a] == rb) {
+                moved = true;
+                if (r.n[a] > 0.0) {
+                    cell[a] += 1;
+                    if (cell[a] >= dims[a]) return kExit;  // rounding guard at the boundary
+                    tnext[a] = ((double)(cell[a] + 1) - r.xs[a]) * r.inv[a];
+                } else {
+                    cell[a] -= 1;
+                    if (cell[a] < 0) return kExit;
+                    tnext[a] = ((double)cell[a] - r.xs[a]) * r.inv[a];
+                }
+            }
+        }
+        if (!moved) {
+            *stuck = true;
+            return kExit;
+        }
+    }
+    *stuck = true;
+    return kExit;
+}
+
+// (1 - e^{-x})/x and 1 - e^{-x} in FP32, accurate for small x.
+__device__ __forceinline__ void absorb_factors(float x, float& phi, float& one_minus_e) {
+    if (x < 0.1f) {
+        phi = 1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f))));
+        one_minus_e = x * phi;
+    } else {
+        one_minus_e = 1.0f - __expf(-x);
+        phi = one_minus_e / x;
+    }
+}
+
+// FP64 versions for the adjoint: phi(x) = (1 - e^{-x})/x given om = 1 - e^{-x},
+// and phi'(x) = (x e^{-x} - (1 - e^{-x}))/x^2, with series near 0.
+__device__ __forceinline__ double absorb_phi(double x, double om) {
+    if (x < 1e-3) return 1.0 - x * (0.5 - x * (1.0 / 6.0 - x * (1.0 / 24.0)));
+    return om / x;
+}
+
+__device__ __forceinline__ double absorb_dphi(double x, double e, double om) {
+    if (x < 1e-3) return -0.5 + x * (1.0 / 3.0 - x * (0.125 - x * (1.0 / 30.0)));
+    return (x * e - om) / (x * x);
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level helpers (wave64)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+}  // namespace art

@@ -125,7 +125,7 @@ class Workload:
 
     def subset(self, idx) -> "Workload":
         """Same grid, only the sources listed in ``idx``."""
-        idx = np.asarray(idx)
+        idx = np.asarray(idx, dtype=np.int64)
         return Workload(name=f"{self.name}[{len(idx)} src]", nx=self.nx, ny=self.ny,
                         nz=self.nz, n_H=self.n_H, x_n=self.x_n,
                         src_pos=np.ascontiguousarray(self.src_pos[idx]),

@@ -1,0 +1,71 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol that
+include/art.h declares, and its error strings resolve (no GPU calls)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "art.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(art_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1711_06277_amd import _abi as A
+    lib = A.lib()
+    names = declared_functions()
+    assert set(names) == set(A.EXPORTED), names
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", A.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines()}
+    assert set(names) <= exported
+
+
+def test_error_strings():
+    from paper_1711_06277_amd import _abi as A
+    assert A.strerror(A.ART_OK) == "ok"
+    for code in range(-7, 0):
+        assert A.strerror(code) != "unknown error"
+    assert A.strerror(-99) == "unknown error"
+
+
+def test_struct_layouts_match_header():
+    """ctypes mirrors of the ABI structs have the sizes the C compiler gives."""
+    import ctypes as C
+    import tempfile
+    from paper_1711_06277_amd import _abi as A
+    src = ('#include "art.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu\\n",'
+           'sizeof(art_params),sizeof(art_options),sizeof(art_stats));return 0;}\n')
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        exe = os.path.join(d, "s")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, c])
+        sizes = [int(x) for x in subprocess.check_output([exe]).split()]
+    assert sizes == [C.sizeof(A.art_params), C.sizeof(A.art_options), C.sizeof(A.art_stats)]
+
+
+def test_create_without_gpu_fails_cleanly():
+    """With no device, art_create returns an error code instead of crashing."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_1711_06277_amd import _abi as A
+    p = A.art_params()
+    p.level0, p.level_max, p.phi_c, p.tau_term, p.s_H, p.n_bins = 2, 13, 4.0, 23.0, 0.1, 1
+    p.rot[0] = p.rot[4] = p.rot[8] = 1.0
+    o = A.art_options()
+    o.max_sources = 1
+    with pytest.raises(A.ArtError):
+        A.art_create(8, 8, 8, p, o, 0)
+    o.max_sources = 0
+    with pytest.raises(A.ArtError) as e:
+        A.art_create(8, 8, 8, p, o, 0)
+    assert e.value.code == A.ART_ERR_INVALID_ARG

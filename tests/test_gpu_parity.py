@@ -1,0 +1,166 @@
+"""GPU parity: the HIP sweep (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bar: ray tree per source and level bit-exact; FP32 cell outputs within 1e-4
+relative on cells above 1e-8 of the batch luminosity; photon conservation
+(sum_c kappa J + escaped + residual = emitted) within 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1711_06277_amd import inputs as I
+from tests.gpu_common import (CONS_TOL, compare_cells, compare_force, conservation, kappas,
+                              run_gpu, tree_equal)
+
+pytestmark = pytest.mark.gpu
+
+
+def check_against_oracle(oracle, wl, **opts):
+    ref = oracle.trace_workload(wl)
+    (rate, force, J), st = run_gpu(wl, want_J=True, **opts)
+    assert st.status == 0, f"device status {st.status}"
+    tree_equal(st, ref)
+    assert st.destroy == st.destroy_expected == wl.n_src * 12 * 4 ** wl.level_max
+    L_tot = float(wl.src_lum.astype(np.float64).sum())
+    e_rate = compare_cells("rate", rate, ref.rate, L_tot)
+    for b in range(wl.n_bins):
+        compare_cells(f"J{b}", J[b], ref.J[b], L_tot)
+    kj = sum(k * j for k, j in zip(kappas(wl), ref.J))
+    e_force = compare_force(force, ref.force, L_tot, kj)
+    cons = conservation(wl, J, st)
+    assert max(cons) <= CONS_TOL, f"photon conservation {cons}"
+    # per-source escaped / residual luminosity (FP64 on both sides)
+    np.testing.assert_allclose(st.src_escaped, ref.escaped, rtol=1e-5, atol=1e-12 * L_tot)
+    np.testing.assert_allclose(st.src_residual, ref.residual, rtol=1e-4, atol=1e-12 * L_tot)
+    seg_ratio = st.segments / max(1, int(ref.segments.sum()))
+    assert abs(seg_ratio - 1) < 1e-4, f"segment count {st.segments} vs oracle {ref.segments.sum()}"
+    print(f"\n{wl.name}: rate err {e_rate:.2e}, force err {e_force}, conservation {cons}, "
+          f"segments {st.segments}")
+    return ref, (rate, force, J), st
+
+
+def small_lognormal(nx=40, ny=36, nz=28, n_src=5, seed=21, n_bins=2, tau_term=I.TAU_TERM_1E10,
+                    s_H=0.3, s_d=0.03):
+    """Ragged (non-cubic) grid, several sources of uneven luminosity, 2 bins."""
+    rng = np.random.default_rng(seed)
+    g = I.lognormal_density(max(nx, ny, nz), 1.5, seed).reshape([max(nx, ny, nz)] * 3)
+    n_H = np.ascontiguousarray(g[:nz, :ny, :nx]).reshape(-1)
+    x_n = rng.uniform(0.0, 1.0, nx * ny * nz).astype(np.float32)
+    pos = np.stack([rng.uniform(0.3, nx - 0.3, n_src), rng.uniform(0.3, ny - 0.3, n_src),
+                    rng.uniform(0.3, nz - 0.3, n_src)], 1)
+    lum = (10 ** rng.uniform(0, 3, (n_src, n_bins))).astype(np.float32)
+    return I.Workload(name=f"ragged {nx}x{ny}x{nz}, {n_src} src", nx=nx, ny=ny, nz=nz,
+                      n_H=n_H, x_n=x_n, src_pos=pos, src_lum=lum, s_H=s_H, s_d=s_d,
+                      n_bins=n_bins, tau_term=tau_term)
+
+
+def test_workload1_uniform(oracle):
+    """32^3 uniform medium, one source: closed-form tree, cells vs oracle."""
+    check_against_oracle(oracle, I.config(1))
+
+
+def test_workload2_turbulent(oracle):
+    """128^3 lognormal (k^-4, std 1.5), source at the density maximum."""
+    ref, _, st = check_against_oracle(oracle, I.config(2))
+    assert ref.terminated.sum() > 0  # the workload exercises tau-termination
+
+
+def test_ragged_multisource_two_bins(oracle):
+    check_against_oracle(oracle, small_lognormal())
+
+
+def test_termination_heavy(oracle):
+    """Low termination threshold: most rays end by optical depth."""
+    wl = small_lognormal(nx=33, ny=31, nz=35, n_src=3, seed=5, tau_term=2.0)
+    ref, _, st = check_against_oracle(oracle, wl)
+    assert ref.terminated.sum() > 0.2 * (ref.terminated.sum() + ref.exited.sum())
+
+
+def test_single_bin_dusty(oracle):
+    wl = small_lognormal(nx=24, ny=40, nz=32, n_src=2, seed=8, n_bins=1)
+    check_against_oracle(oracle, wl)
+
+
+def test_deterministic_mode_bitwise(oracle):
+    """Fixed-point deposits: two runs are bitwise equal, and match the oracle."""
+    wl = small_lognormal(seed=33)
+    check_against_oracle(oracle, wl, deterministic=True)
+    (r1, f1, J1), _ = run_gpu(wl, deterministic=True)
+    (r2, f2, J2), _ = run_gpu(wl, deterministic=True)
+    assert np.array_equal(r1, r2) and np.array_equal(f1, f2) and np.array_equal(J1, J2)
+
+
+def test_many_waves_match_one_wave(oracle):
+    """A pool that holds one source at a time (several waves) gives the same
+    tree and cells as the oracle."""
+    wl = small_lognormal(nx=24, ny=24, nz=24, n_src=4, seed=2)
+    bound_one = 400000
+    ref, _, st = check_against_oracle(oracle, wl, pool_rays=bound_one)
+    assert st.n_waves > 1
+
+
+def test_level0_equals_level_max(oracle):
+    """No splitting at all: every ray is a level-l0 ray to the boundary."""
+    wl = small_lognormal(nx=20, ny=20, nz=20, n_src=2, seed=3)
+    wl.level0, wl.level_max = 3, 3
+    check_against_oracle(oracle, wl)
+
+
+def test_vacuum(oracle):
+    """s_H = s_d = 0: nothing absorbed, J follows the oracle (1/r^2 law)."""
+    wl = I.uniform_workload(32, [15.2, 17.9, 16.4], lum=1.0, s_H=0.0, s_d=0.0, n_bins=1,
+                            level0=4)
+    ref = oracle.trace_workload(wl)
+    (rate, force, J), st = run_gpu(wl)
+    tree_equal(st, ref)
+    compare_cells("J", J[0], ref.J[0], 1.0)
+    assert np.abs(rate).max() == 0.0 and np.abs(force).max() == 0.0
+    np.testing.assert_allclose(st.src_escaped[:, 0], 1.0, rtol=1e-12)
+
+
+def test_no_sources():
+    wl = small_lognormal(n_src=1)
+    wl = wl.subset([])
+    (rate, force, J), st = run_gpu(wl)
+    assert st.status == 0 and st.segments == 0
+    assert not rate.any() and not force.any() and not J.any()
+
+
+def test_source_outside_is_reported():
+    from paper_1711_06277_amd._abi import ART_ERR_SOURCE_OUTSIDE, ArtError
+    wl = small_lognormal(n_src=2)
+    wl.src_pos = wl.src_pos.copy()
+    wl.src_pos[1, 0] = wl.nx + 3.0
+    with pytest.raises(ArtError) as e:
+        run_gpu(wl)
+    assert e.value.code == ART_ERR_SOURCE_OUTSIDE
+
+
+def test_pool_overflow_is_reported():
+    from paper_1711_06277_amd._abi import ART_ERR_QUEUE_OVERFLOW, ArtError
+    wl = small_lognormal(nx=32, ny=32, nz=32, n_src=1)
+    with pytest.raises(ArtError) as e:
+        run_gpu(wl, pool_rays=12 * 16 + 100)
+    assert e.value.code == ART_ERR_QUEUE_OVERFLOW
+
+
+@pytest.mark.parametrize("phi_c", [2.0, 10.0])
+def test_other_m_ray(oracle, phi_c):
+    wl = small_lognormal(nx=28, ny=28, nz=28, n_src=2, seed=12)
+    wl.phi_c = phi_c
+    check_against_oracle(oracle, wl)
+
+
+def test_rotated_directions(oracle):
+    wl = small_lognormal(nx=24, ny=26, nz=22, n_src=2, seed=4)
+    th = 0.37
+    rot = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]])
+    c, s = math.cos(0.2), math.sin(0.2)
+    rot = rot @ np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+    ref = oracle.trace_workload(wl, rot=rot)
+    (rate, force, J), st = run_gpu(wl, rot=rot)
+    tree_equal(st, ref)
+    compare_cells("rate", rate, ref.rate, float(wl.src_lum.sum()))
+
