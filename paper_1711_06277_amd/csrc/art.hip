@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "art_device.h"
@@ -91,11 +92,9 @@ struct SweepArgs {
     Pool pool;
     Counters* ct;
     SrcStats st;
-    // FP32 deposit targets (atomic mode)
-    float* J0;
-    float* J1;   // may be null
-    float* F;    // [3][N]
-    // fixed-point targets (deterministic mode): [5][N] = J0, J1, Fx, Fy, Fz
+    // deposit accumulators, one cell's values contiguous (AoS, stride 4 or 8):
+    // J0, Fx, Fy, Fz[, J1]; FP32 (atomic mode) or 64-bit fixed point
+    float* acc;
     unsigned long long* det;
     uint32_t N;
     uint32_t n_src;
@@ -111,8 +110,8 @@ struct AdjArgs {
     const float* v;   // [3][N]
     Pool pool;
     Counters* ct;
-    double* gk;                // [2][N] dL/dkappa_b, FP64 atomics
-    unsigned long long* gdet;  // [2][N] fixed point
+    double* gk;                // [2][N] dL/dn_H, dL/dx_n (FP64 atomics)
+    unsigned long long* gdet;  // [2][N] the same in fixed point
     uint32_t N;
     uint32_t n_src;
 };
@@ -173,39 +172,47 @@ __global__ void k_begin_call(Counters* ct, const float* src_lum, int n_lum) {
     }
 }
 
-// Fixed-point scale of the adjoint: |dL/dkappa| per cell is bounded by a few
-// times L_total (max w + sqrt(3) max |v|), see the adjoint kernel.
-__global__ void k_adj_scale(Counters* ct, const float* w, const float* v, uint64_t N,
-                            const float* src_lum, int n_lum, float* scratch_max) {
-    __shared__ float part[256];
-    float m = 0.0f;
+// Fixed-point scale of the adjoint.  Per cell, |dL/dkappa_b| <= 4 W L_total with
+// W = max w + sqrt(3) max |v| (every downstream contribution of a ray is at
+// most W times its packet, and sum over rays of packet x dr is at most the
+// vacuum J <= sqrt(3) L_total); dL/dn_H and dL/dx_n add the chain-rule factors
+// (x_n s_H + s_d) <= s_H + s_d and n_H s_H <= max(n_H) s_H.  scratch[0] = W,
+// scratch[1] = max n_H (float bit patterns, non-negative, so unsigned max works).
+__global__ void k_adj_scale(const float* w, const float* v, const float* nH, uint64_t N, float* scratch) {
+    __shared__ float pw[256], pn[256];
+    float m = 0.0f, mn = 0.0f;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        m = fmaxf(m, fabsf(w[i]));
         const float vv = fabsf(v[i]) + fabsf(v[N + i]) + fabsf(v[2 * N + i]);
-        m = fmaxf(m, 1.7320508f * vv);
+        m = fmaxf(m, fabsf(w[i]) + 1.7320508f * vv);
+        mn = fmaxf(mn, fabsf(nH[i]));
     }
-    part[threadIdx.x] = m;
+    pw[threadIdx.x] = m;
+    pn[threadIdx.x] = mn;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) part[threadIdx.x] = fmaxf(part[threadIdx.x], part[threadIdx.x + o]);
+        if ((int)threadIdx.x < o) {
+            pw[threadIdx.x] = fmaxf(pw[threadIdx.x], pw[threadIdx.x + o]);
+            pn[threadIdx.x] = fmaxf(pn[threadIdx.x], pn[threadIdx.x + o]);
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax((unsigned int*)scratch_max, __float_as_uint(part[0]));
-    (void)ct;
-    (void)src_lum;
-    (void)n_lum;
+    if (threadIdx.x == 0) {
+        atomicMax((unsigned int*)&scratch[0], __float_as_uint(pw[0]));
+        atomicMax((unsigned int*)&scratch[1], __float_as_uint(pn[0]));
+    }
 }
 
-__global__ void k_adj_scale_final(Counters* ct, const float* src_lum, int n_lum, const float* scratch_max,
-                                  double s_H_max) {
+__global__ void k_adj_scale_final(Counters* ct, const float* src_lum, int n_lum, const float* scratch,
+                                  double s_H, double s_d) {
     if (threadIdx.x != 0) return;
     double L = 0.0;
     for (int i = 0; i < n_lum; ++i) L += fabs((double)src_lum[i]);
     if (!(L > 0.0)) L = 1.0;
-    double W = (double)(*scratch_max) * (1.0 + s_H_max);
+    double W = (double)scratch[0];
     if (!(W > 0.0)) W = 1.0;
-    const double bound = 8.0 * W * L;
+    const double chain = 1.0 + s_H + s_d + s_H * (double)scratch[1];
+    const double bound = 8.0 * W * L * chain;
     ct->c.gscale = ldexp(1.0, 58) / bound;
     ct->c.inv_gscale = bound * ldexp(1.0, -58);
 }
@@ -236,13 +243,158 @@ __global__ void k_seed(Pool pool, Counters* ct, int level0, int src0, int n_wave
 }
 
 // --------------------------------------------------------------------------
+// Per-wavefront LDS write-back cache of deposits
+// --------------------------------------------------------------------------
+
+// The 64 lanes of a wavefront trace neighbouring directions of one source, so
+// their segments keep landing in the same few cells.  Global atomics cost one
+// memory transaction per cache line touched (scattered single-lane atomics run
+// ~15x slower than atomics on 64 consecutive words), so deposits go through
+// two stages in LDS:
+//   1. a direct-mapped cache of S cells (slot = the cell's position in an
+//      8 x 8 x (S/64) tile) accumulated with LDS atomics;
+//   2. cells evicted from it (or that lost a slot) are appended to a staging
+//      list, which the whole wavefront flushes in converged code: lane l adds
+//      value (l mod LPE) of staged cell (l / LPE), so the NV values of a cell,
+//      contiguous in the AoS accumulator, share one memory transaction.
+// Every step is executed in program order by the active lanes of one
+// wavefront and LDS executes a wavefront's instructions in order, so no barrier
+// is needed; keys, owners and the staging count are volatile (re-read from LDS).
+constexpr uint32_t kEmptyKey = 0xffffffffu;
+#define ART_LDS __attribute__((address_space(3)))
+
+template <int NV, bool DET>
+struct Deposit {
+    using V = typename std::conditional<DET, unsigned long long, float>::type;
+    static constexpr int S = 256;          // cache slots
+    static constexpr int CAP = 128;        // staging capacity (>= 64 + flush threshold)
+    static constexpr int LPE = NV <= 4 ? 4 : 8;  // lanes per staged cell = AoS stride
+    volatile ART_LDS uint32_t* keys;       // [S]
+    volatile ART_LDS uint8_t* own;         // [S]
+    ART_LDS V* vals;                       // [NV][S]
+    volatile ART_LDS uint32_t* n_staged;   // [1]
+    ART_LDS uint32_t* skey;                // [CAP]
+    ART_LDS V* sval;                       // [NV][CAP]
+
+    __device__ static inline uint32_t slot(const int (&ijk)[3]) {
+        return (uint32_t)((ijk[0] & 7) | ((ijk[1] & 7) << 3) | ((ijk[2] & 3) << 6));
+    }
+    __device__ static inline void lds_add(ART_LDS float* p, float x) {
+        __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+    __device__ static inline void lds_add(ART_LDS unsigned long long* p, unsigned long long x) {
+        __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+
+    __device__ inline void init(int lane) {
+        for (int s = lane; s < S; s += kWave) keys[s] = kEmptyKey;
+        if (lane == 0) *n_staged = 0u;
+    }
+
+    __device__ inline void stage(uint32_t c, const V (&v)[NV]) {
+        const uint32_t e = __hip_atomic_fetch_add((ART_LDS uint32_t*)n_staged, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WAVEFRONT);
+        skey[e] = c;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sval[q * CAP + e] = v[q];
+    }
+
+    // Active lanes only (any subset of the wavefront).
+    __device__ inline void deposit(uint32_t c, const int (&ijk)[3], const V (&v)[NV], int lane) {
+        const uint32_t h = slot(ijk);
+        const uint32_t key0 = keys[h];
+        const bool hit = key0 == c;
+        if (hit) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) lds_add(&vals[q * S + h], v[q]);
+        }
+        bool claimed = false, owner = false;
+        if (!hit) {
+            keys[h] = c;
+            claimed = keys[h] == c;
+        }
+        if (claimed) {
+            own[h] = (uint8_t)lane;
+            owner = own[h] == (uint8_t)lane;
+        }
+        if (owner) {
+            if (key0 != kEmptyKey) {
+                V old[NV];
+#pragma unroll
+                for (int q = 0; q < NV; ++q) old[q] = vals[q * S + h];
+                stage(key0, old);
+            }
+#pragma unroll
+            for (int q = 0; q < NV; ++q) vals[q * S + h] = v[q];
+        }
+        if (claimed && !owner) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) lds_add(&vals[q * S + h], v[q]);
+        }
+        if (!hit && !claimed) stage(c, v);
+    }
+
+    // Converged: the whole wavefront writes the staged cells to the AoS
+    // accumulator (stride LPE) when at least `threshold` are staged.
+    __device__ inline void flush(V* acc, int lane, uint32_t threshold) {
+        const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)*n_staged);
+        if (n < threshold || n == 0) return;
+        const uint32_t per = kWave / LPE;
+        const int f = lane % LPE;
+        for (uint32_t b0 = 0; b0 < n; b0 += per) {
+            const uint32_t e = b0 + (uint32_t)lane / LPE;
+            if (e < n && f < NV) {
+                V* p = acc + (uint64_t)skey[e] * LPE + f;
+                const V x = sval[f * CAP + e];
+                if (DET) atomicAdd((unsigned long long*)p, (unsigned long long)x);
+                else unsafeAtomicAdd((float*)p, (float)x);
+            }
+        }
+        if (lane == 0) *n_staged = 0u;
+    }
+
+    // Converged: empty the cache into the accumulator.
+    __device__ inline void drain(V* acc, int lane) {
+        for (int s0 = 0; s0 < S; s0 += kWave) {
+            const int s = s0 + lane;
+            const uint32_t k = keys[s];
+            if (k != kEmptyKey) {
+                V old[NV];
+#pragma unroll
+                for (int q = 0; q < NV; ++q) old[q] = vals[q * S + s];
+                stage(k, old);
+                keys[s] = kEmptyKey;
+            }
+            flush(acc, lane, 1u);
+        }
+    }
+};
+
+// --------------------------------------------------------------------------
 // Forward sweep of one level
 // --------------------------------------------------------------------------
 
-// DET: fixed-point deposits.  FULL: deposit force (and J1); otherwise only J0
-// (the tape pass of the adjoint needs J0 for the explicit rate term).
-template <int NB, bool DET, bool FULL>
+// MODE 0: tree only (the tape pass of the adjoint); 1: J0 and the force;
+// 2: also J1 (the non-ionizing bin's J).  DET: 64-bit fixed-point deposits.
+template <int MODE>
+struct SweepVals {
+    static constexpr int NV = MODE == 2 ? 5 : 4;
+};
+
+template <int NB, bool DET, int MODE>
 __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
+    constexpr int NV = SweepVals<MODE>::NV;
+    using Dep = Deposit<NV, DET>;
+    using V = typename Dep::V;
+    constexpr int NW = 4;                       // wavefronts per workgroup (block size <= 256)
+    constexpr int SS = MODE ? Dep::S : 1;
+    constexpr int SC = MODE ? Dep::CAP : 1;
+    __shared__ uint32_t sh_keys[NW][SS];
+    __shared__ uint8_t sh_own[NW][SS];
+    __shared__ V sh_vals[NW][NV * SS];
+    __shared__ uint32_t sh_n[NW];
+    __shared__ uint32_t sh_skey[NW][SC];
+    __shared__ V sh_sval[NW][NV * SC];
     const Geo& g = a.g;
     Counters* ct = a.ct;
     const int lane = lane_id();
@@ -255,10 +407,19 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
     const uint64_t off_next = off + n_level;
     const int next = level + 1;
     if (blockIdx.x == 0 && threadIdx.x == 0 && next <= ART_MAX_LEVELS) ct->w.off[next] = off_next;
-    const uint32_t N = a.N;
     const double scale = DET ? ct->c.scale : 0.0;
     const float lnom_scale = ldexpf(1.0f / 12.0f, -2 * level);  // 1 / N_ray(l)
     const unsigned long long dweight = 1ull << (2 * (g.level_max - level));
+    V* acc = (V*)(DET ? (void*)a.det : (void*)a.acc);
+
+    const int w = (int)(threadIdx.x >> 6);
+    Dep dep{(volatile ART_LDS uint32_t*)sh_keys[w], (volatile ART_LDS uint8_t*)sh_own[w], (ART_LDS V*)sh_vals[w],
+            (volatile ART_LDS uint32_t*)&sh_n[w], (ART_LDS uint32_t*)sh_skey[w], (ART_LDS V*)sh_sval[w]};
+    if (MODE) dep.init(lane);
+    auto quant = [&](float x) -> V {
+        if (DET) return (V)(unsigned long long)__double2ll_rn((double)x * scale);
+        else return (V)x;
+    };
 
     for (;;) {
         // Every lane claims one ray.  The uniform-address atomic is combined by
@@ -272,7 +433,6 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
         const uint64_t slot = off + (active ? li : 0u);
 
         uint32_t src = 0, pix = 0;
-        int end = kExit;
         uint32_t nseg = 0;
         double left[NB];
         double tau[NB];
@@ -282,6 +442,13 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
             tau[b] = 0.0;
         }
         bool bad_src = false, stuck = false;
+        Ray r;
+        MarchState m;
+        m.alive = false;
+        m.end = kExit;
+        float lnom[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) lnom[b] = 0.0f;
         if (active) {
             src = a.pool.src[slot];
             pix = a.pool.pix[slot];
@@ -291,22 +458,23 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
             }
 #pragma unroll
             for (int b = 0; b < NB; ++b) tau[b] = a.pool.tau[2 * slot + b];
-            Ray r;
             ray_setup(g, a.src_pos, src, level, pix, r);
-            float lnom[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) lnom[b] = a.src_lum[(uint64_t)src * NB + b] * lnom_scale;
-            if (bad_src || !source_inside(g, r.xs)) {
-                bad_src = true;
-                end = kExit;
-            } else if (r.starts_outside) {
-                end = kExit;
-            } else {
-                const float nx = (float)r.n[0], ny = (float)r.n[1], nz = (float)r.n[2];
-                end = march<NB>(g, a.nH, a.xn, r, tau, &stuck,
-                    [&](uint32_t c, double dr, const double (&dtau)[NB], const double (&tin)[NB]) {
+            if (bad_src || !source_inside(g, r.xs)) bad_src = true;
+            else if (!r.starts_outside) march_begin(g, r, m);
+        }
+        // converged march: one segment per lane per iteration
+        while (__ballot(m.alive)) {
+            if (m.alive) {
+                uint32_t c;
+                int ijk[3];
+                double dr, dtau[NB], tin[NB];
+                if (march_step<NB>(g, a.nH, a.xn, r, m, tau, &stuck, c, ijk, dr, dtau, tin)) {
+                    ++nseg;
+                    if (MODE) {
                         const float drf = (float)dr;
-                        float dLs = 0.0f;
+                        float dLs = 0.0f, j0 = 0.0f, j1 = 0.0f;
 #pragma unroll
                         for (int b = 0; b < NB; ++b) {
                             const float x = (float)dtau[b];
@@ -314,35 +482,26 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
                             float ph, om;
                             absorb_factors(x, ph, om);
                             dLs += Lin * om;
-                            const float jv = Lin * drf * ph;
-                            if (b == 0) {
-                                if (DET) fx_add(&a.det[c], (double)jv, scale);
-                                else unsafeAtomicAdd(&a.J0[c], jv);
-                            } else if (FULL) {
-                                if (DET) fx_add(&a.det[(uint64_t)N + c], (double)jv, scale);
-                                else if (a.J1) unsafeAtomicAdd(&a.J1[c], jv);
-                            }
+                            if (b == 0) j0 = Lin * drf * ph;
+                            else j1 = Lin * drf * ph;
                         }
-                        if (FULL) {
-                            if (DET) {
-                                fx_add(&a.det[2ull * N + c], (double)(nx * dLs), scale);
-                                fx_add(&a.det[3ull * N + c], (double)(ny * dLs), scale);
-                                fx_add(&a.det[4ull * N + c], (double)(nz * dLs), scale);
-                            } else {
-                                unsafeAtomicAdd(&a.F[c], nx * dLs);
-                                unsafeAtomicAdd(&a.F[(uint64_t)N + c], ny * dLs);
-                                unsafeAtomicAdd(&a.F[2ull * N + c], nz * dLs);
-                            }
-                        }
-                        ++nseg;
-                    });
+                        V v[NV];
+                        v[0] = quant(j0);
+                        v[1] = quant((float)r.n[0] * dLs);
+                        v[2] = quant((float)r.n[1] * dLs);
+                        v[3] = quant((float)r.n[2] * dLs);
+                        if (NV > 4) v[4 % NV] = quant(j1);
+                        dep.deposit(c, ijk, v, lane);
+                    }
+                }
             }
-            if (end != kSplit) {
+            if (MODE) dep.flush(acc, lane, 64u);
+        }
+        const int end = m.end;
+        if (active && end != kSplit) {
 #pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    left[b] = (double)a.src_lum[(uint64_t)src * NB + b] / (12.0 * ldexp(1.0, 2 * level)) *
-                              exp(-tau[b]);
-            }
+            for (int b = 0; b < NB; ++b)
+                left[b] = (double)a.src_lum[(uint64_t)src * NB + b] / (12.0 * ldexp(1.0, 2 * level)) * exp(-tau[b]);
         }
         if (__ballot(bad_src)) {
             if (lane == 0) atomicOr(&ct->c.status, (uint32_t)kStOutside);
@@ -419,6 +578,7 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
             }
         }
     }
+    if (MODE) dep.drain(acc, lane);
 }
 
 // After the deepest level of a wave: record the number of rays the wave held.
@@ -429,28 +589,31 @@ __global__ void k_end_wave(Counters* ct, int level0, int level_max) {
     atomicMax(&ct->c.rays_wave_max, tot);
 }
 
-// rate = s_H x_n n_H J_0 (Eq. e:photrate2); unpack fixed point; copy J.
+// rate = s_H x_n n_H J_0 (Eq. e:photrate2); force and J from the AoS
+// accumulator (stride LPE), unpacking fixed point in deterministic mode.
 template <bool DET>
-__global__ void k_finalize(uint64_t N, const float* nH, const float* xn, double s_H, const float* J0,
-                           const unsigned long long* det, const Counters* ct, float* rate, float* force,
+__global__ void k_finalize(uint64_t N, const float* nH, const float* xn, double s_H, const float* acc,
+                           const unsigned long long* det, int lpe, const Counters* ct, float* rate, float* force,
                            float* J, int n_bins) {
     const double inv = DET ? ct->c.inv_scale : 0.0;
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N;
          c += (uint64_t)gridDim.x * blockDim.x) {
-        double j0;
-        if (DET) j0 = (double)(long long)det[c] * inv;
-        else j0 = (double)J0[c];
-        rate[c] = (float)(s_H * (double)xn[c] * (double)nH[c] * j0);
-        if (DET) {
-            force[c] = (float)((double)(long long)det[2 * N + c] * inv);
-            force[N + c] = (float)((double)(long long)det[3 * N + c] * inv);
-            force[2 * N + c] = (float)((double)(long long)det[4 * N + c] * inv);
-            if (J) {
-                J[c] = (float)j0;
-                if (n_bins > 1) J[N + c] = (float)((double)(long long)det[N + c] * inv);
+        double v[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            if (f >= 4 && lpe < 8) {
+                v[f] = 0.0;
+                continue;
             }
-        } else if (J) {
-            J[c] = (float)j0;
+            v[f] = DET ? (double)(long long)det[c * lpe + f] * inv : (double)acc[c * lpe + f];
+        }
+        rate[c] = (float)(s_H * (double)xn[c] * (double)nH[c] * v[0]);
+        force[c] = (float)v[1];
+        force[N + c] = (float)v[2];
+        force[2 * N + c] = (float)v[3];
+        if (J) {
+            J[c] = (float)v[0];
+            if (n_bins > 1) J[N + c] = (float)v[4];
         }
     }
 }
@@ -507,7 +670,7 @@ __device__ inline void adjoint_ray(const AdjArgs& a, Counters* ct, int level, ui
 #pragma unroll
         for (int b = 0; b < NB; ++b) tau[b] = tau0[b];
         march<NB>(g, a.nH, a.xn, r, tau, &stuck,
-            [&](uint32_t c, double dr, const double (&dtau)[NB], const double (&tin)[NB]) {
+            [&](uint32_t c, const int (&ijk)[3], double dr, const double (&dtau)[NB], const double (&tin)[NB]) {
                 const double wa = (double)a.w[c] * sH * (double)a.xn[c] * (double)a.nH[c];
                 const double beta = (double)a.v[c] * r.n[0] + (double)a.v[(uint64_t)N + c] * r.n[1] +
                                     (double)a.v[2ull * N + c] * r.n[2];
@@ -529,10 +692,11 @@ __device__ inline void adjoint_ray(const AdjArgs& a, Counters* ct, int level, ui
             tau[b] = tau0[b];
         }
         march<NB>(g, a.nH, a.xn, r, tau, &stuck,
-            [&](uint32_t c, double dr, const double (&dtau)[NB], const double (&tin)[NB]) {
+            [&](uint32_t c, const int (&ijk)[3], double dr, const double (&dtau)[NB], const double (&tin)[NB]) {
                 const double wa = (double)a.w[c] * sH * (double)a.xn[c] * (double)a.nH[c];
                 const double beta = (double)a.v[c] * r.n[0] + (double)a.v[(uint64_t)N + c] * r.n[1] +
                                     (double)a.v[2ull * N + c] * r.n[2];
+                double dkap[NB];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     const double x = dtau[b];
@@ -547,9 +711,22 @@ __device__ inline void adjoint_ray(const AdjArgs& a, Counters* ct, int level, ui
                     }
                     P[b] += own;
                     const double after = (T[b] - P[b]) + Gend[b];
-                    const double d = dk - dr * after;
-                    if (DET) fx_add(&a.gdet[(uint64_t)b * N + c], d, gscale);
-                    else unsafeAtomicAdd(&a.gk[(uint64_t)b * N + c], d);
+                    dkap[b] = dk - dr * after;
+                }
+                // chain rule through kappa_0 = n_H (x_n s_H + s_d), kappa_1 = n_H s_d,
+                // plus the explicit n_H x_n factor of rate = s_H x_n n_H J_0
+                const double xv = (double)a.xn[c], nv = (double)a.nH[c];
+                const double j0 = lnom[0] * exp(-tin[0]) * dr * absorb_phi(dtau[0], -expm1(-dtau[0]));
+                const double wj = (double)a.w[c] * sH * j0;
+                double gn = dkap[0] * (xv * sH + g.s_d) + wj * xv;
+                if (NB > 1) gn += dkap[NB - 1] * g.s_d;
+                const double gx = dkap[0] * nv * sH + wj * nv;
+                if (DET) {
+                    fx_add(&a.gdet[c], gn, gscale);
+                    fx_add(&a.gdet[(uint64_t)N + c], gx, gscale);
+                } else {
+                    unsafeAtomicAdd(&a.gk[c], gn);
+                    unsafeAtomicAdd(&a.gk[(uint64_t)N + c], gx);
                 }
             });
         if (stuck) atomicOr(&ct->c.status, (uint32_t)kStStuck);
@@ -573,29 +750,20 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
     }
 }
 
-// g_nH = dL/dk0 (x_n s_H + s_d) + dL/dk1 s_d + w s_H x_n J0;  g_xn = dL/dk0 n_H s_H + w s_H n_H J0
+// Convert the accumulated dL/dn_H and dL/dx_n to the FP32 outputs.
 template <bool DET>
-__global__ void k_adj_finalize(uint64_t N, int n_bins, const float* nH, const float* xn, double s_H,
-                               double s_d, const float* w, const float* J0, const unsigned long long* det,
-                               const double* gk, const unsigned long long* gdet, const Counters* ct,
+__global__ void k_adj_finalize(uint64_t N, const double* gk, const unsigned long long* gdet, const Counters* ct,
                                float* g_nH, float* g_xn) {
-    const double inv = DET ? ct->c.inv_scale : 0.0;
     const double ginv = DET ? ct->c.inv_gscale : 0.0;
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N;
          c += (uint64_t)gridDim.x * blockDim.x) {
-        double j0, k0, k1 = 0.0;
         if (DET) {
-            j0 = (double)(long long)det[c] * inv;
-            k0 = (double)(long long)gdet[c] * ginv;
-            if (n_bins > 1) k1 = (double)(long long)gdet[N + c] * ginv;
+            g_nH[c] = (float)((double)(long long)gdet[c] * ginv);
+            g_xn[c] = (float)((double)(long long)gdet[N + c] * ginv);
         } else {
-            j0 = (double)J0[c];
-            k0 = gk[c];
-            if (n_bins > 1) k1 = gk[N + c];
+            g_nH[c] = (float)gk[c];
+            g_xn[c] = (float)gk[N + c];
         }
-        const double x = (double)xn[c], n = (double)nH[c], ww = (double)w[c];
-        g_nH[c] = (float)(k0 * (x * s_H + s_d) + k1 * s_d + ww * s_H * x * j0);
-        g_xn[c] = (float)(k0 * n * s_H + ww * s_H * n * j0);
     }
 }
 
@@ -619,8 +787,8 @@ struct art_ctx {
     int wave_max;
     Counters* ct;
     SrcStats st;
-    float* J0;
-    unsigned long long* det;
+    float* acc;              // [8][N] AoS deposit accumulator (atomic mode)
+    unsigned long long* det; // [8][N] the same in fixed point (deterministic mode)
     double* gk;
     unsigned long long* gdet;
     float* fscratch;
@@ -735,7 +903,7 @@ void free_all(art_ctx* c) {
     (void)hipFree(c->st.escaped);
     (void)hipFree(c->st.residual);
     (void)hipFree(c->st.segments);
-    (void)hipFree(c->J0);
+    (void)hipFree(c->acc);
     (void)hipFree(c->det);
     (void)hipFree(c->gk);
     (void)hipFree(c->gdet);
@@ -763,28 +931,30 @@ SweepArgs sweep_args(art_ctx* c, const float* nH, const float* xn, const double*
     a.pool = c->pool;
     a.ct = c->ct;
     a.st = c->st;
-    a.J0 = c->J0;
-    a.J1 = (J && c->p.n_bins > 1) ? J + c->N : nullptr;
-    a.F = force;
+    a.acc = c->acc;
+    (void)force;
+    (void)J;
     a.det = c->det;
     a.N = (uint32_t)c->N;
     a.n_src = (uint32_t)n_src;
     return a;
 }
 
-int launch_sweep(art_ctx* c, const SweepArgs& a, int level, bool full) {
+// mode 0: J0 only (adjoint tape pass); 1: J0 + force; 2: J0 + force + J1
+int launch_sweep(art_ctx* c, const SweepArgs& a, int level, int mode) {
     const dim3 grid((unsigned)(c->cu_count * c->o.blocks_per_cu)), block((unsigned)c->o.block_size);
     const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
     const int nb = c->p.n_bins;
     const bool tm = c->timing && c->ev_used + 2 <= (int)c->ev.size();
     if (tm) HIP_TRY(hipEventRecord(c->ev[c->ev_used], c->stream));
-#define SWEEP(NB, DET, FULL) hipLaunchKernelGGL((k_sweep<NB, DET, FULL>), grid, block, 0, c->stream, a, level)
+#define SWEEP(NB, DET, MODE) hipLaunchKernelGGL((k_sweep<NB, DET, MODE>), grid, block, 0, c->stream, a, level)
     if (nb == 1) {
-        if (det) { if (full) SWEEP(1, true, true); else SWEEP(1, true, false); }
-        else { if (full) SWEEP(1, false, true); else SWEEP(1, false, false); }
+        if (det) { if (mode) SWEEP(1, true, 1); else SWEEP(1, true, 0); }
+        else { if (mode) SWEEP(1, false, 1); else SWEEP(1, false, 0); }
+    } else if (det) {
+        if (mode == 2) SWEEP(2, true, 2); else if (mode == 1) SWEEP(2, true, 1); else SWEEP(2, true, 0);
     } else {
-        if (det) { if (full) SWEEP(2, true, true); else SWEEP(2, true, false); }
-        else { if (full) SWEEP(2, false, true); else SWEEP(2, false, false); }
+        if (mode == 2) SWEEP(2, false, 2); else if (mode == 1) SWEEP(2, false, 1); else SWEEP(2, false, 0);
     }
 #undef SWEEP
     HIP_TRY(hipGetLastError());
@@ -818,9 +988,9 @@ int seed_wave(art_ctx* c, int s0, int n_wave) {
 }
 
 // Sweep every level of the current wave, l0 first.
-int sweep_wave(art_ctx* c, const SweepArgs& a, bool full) {
+int sweep_wave(art_ctx* c, const SweepArgs& a, int mode) {
     for (int l = c->p.level0; l <= c->p.level_max; ++l) {
-        int rc = launch_sweep(c, a, l, full);
+        int rc = launch_sweep(c, a, l, mode);
         if (rc) return rc;
     }
     hipLaunchKernelGGL(k_end_wave, dim3(1), dim3(64), 0, c->stream, c->ct, c->p.level0, c->p.level_max);
@@ -933,7 +1103,7 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
               dmalloc(&c->st.residual, ms * 2) && dmalloc(&c->st.segments, ms) && dmalloc(&c->fscratch, 64);
     if (ok && o.enable_adjoint)
         ok = dmalloc(&c->pool.child, cap) && dmalloc(&c->pool.G, 2 * cap);
-    if (ok) ok = det ? dmalloc(&c->det, 5 * N) : dmalloc(&c->J0, N);
+    if (ok) ok = det ? dmalloc(&c->det, 8 * N) : dmalloc(&c->acc, 8 * N);
     if (ok && o.enable_adjoint) ok = det ? dmalloc(&c->gdet, 2 * N) : dmalloc(&c->gk, 2 * N);
     if (ok) {
         c->ev.resize(2 * (ART_MAX_LEVELS + 1) * 64);
@@ -969,12 +1139,12 @@ int art_trace(art_ctx* c, const float* n_H, const float* x_n, const double* src_
     if (c->timing) HIP_TRY(hipEventRecord(c->ev_call0, c->stream));
     int rc;
     if ((rc = begin_call(c, src_lum, n_src))) return rc;
-    if ((rc = zero(c, force, 3 * N))) return rc;
+    const int mode = (J && c->p.n_bins > 1) ? 2 : 1;
+    const int lpe = mode == 2 ? 8 : 4;
     if (det) {
-        if ((rc = zero(c, c->det, 5 * N))) return rc;
-    } else {
-        if ((rc = zero(c, c->J0, N))) return rc;
-        if (J && c->p.n_bins > 1 && (rc = zero(c, J + N, N))) return rc;
+        if ((rc = zero(c, c->det, (uint64_t)lpe * N))) return rc;
+    } else if ((rc = zero(c, c->acc, (uint64_t)lpe * N))) {
+        return rc;
     }
     if ((rc = zero(c, c->st.created, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.split, ms * ART_MAX_LEVELS)) ||
         (rc = zero(c, c->st.exited, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.term, ms * ART_MAX_LEVELS)) ||
@@ -986,15 +1156,15 @@ int art_trace(art_ctx* c, const float* n_H, const float* x_n, const double* src_
     for (int s0 = 0; s0 < n_src; s0 += c->wave_max) {
         const int nw = std::min(c->wave_max, n_src - s0);
         if ((rc = seed_wave(c, s0, nw))) return rc;
-        if ((rc = sweep_wave(c, a, true))) return rc;
+        if ((rc = sweep_wave(c, a, mode))) return rc;
         ++waves;
     }
     const dim3 fg(fill_blocks(N)), fb(256);
     if (det)
-        hipLaunchKernelGGL((k_finalize<true>), fg, fb, 0, c->stream, N, n_H, x_n, c->p.s_H, c->J0, c->det, c->ct,
-                           rate, force, J, c->p.n_bins);
+        hipLaunchKernelGGL((k_finalize<true>), fg, fb, 0, c->stream, N, n_H, x_n, c->p.s_H, c->acc, c->det, lpe,
+                           c->ct, rate, force, J, c->p.n_bins);
     else
-        hipLaunchKernelGGL((k_finalize<false>), fg, fb, 0, c->stream, N, n_H, x_n, c->p.s_H, c->J0, c->det,
+        hipLaunchKernelGGL((k_finalize<false>), fg, fb, 0, c->stream, N, n_H, x_n, c->p.s_H, c->acc, c->det, lpe,
                            c->ct, rate, force, J, c->p.n_bins);
     HIP_TRY(hipGetLastError());
     if (c->timing) HIP_TRY(hipEventRecord(c->ev_call1, c->stream));
@@ -1023,13 +1193,12 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
     const bool reuse = c->tape_ok && c->tape_key[0] == n_H && c->tape_key[1] == x_n &&
                        c->tape_key[2] == src_pos && c->tape_key[3] == src_lum && c->tape_nsrc == n_src;
     if (det) {
-        if ((rc = zero(c, (uint32_t*)c->fscratch, 1))) return rc;
+        if ((rc = zero(c, (uint32_t*)c->fscratch, 2))) return rc;
         hipLaunchKernelGGL(k_adj_scale, dim3(fill_blocks(N) < 1024 ? fill_blocks(N) : 1024), dim3(256), 0,
-                           c->stream, c->ct, g_rate, g_force, N, src_lum, n_src * c->p.n_bins, c->fscratch);
+                           c->stream, g_rate, g_force, n_H, N, c->fscratch);
         HIP_TRY(hipGetLastError());
-        double sHmax = c->p.s_H + c->p.s_d;
         hipLaunchKernelGGL(k_adj_scale_final, dim3(1), dim3(64), 0, c->stream, c->ct, src_lum, n_src * c->p.n_bins,
-                           c->fscratch, sHmax);
+                           c->fscratch, c->p.s_H, c->p.s_d);
         HIP_TRY(hipGetLastError());
         if ((rc = zero(c, c->gdet, 2 * N))) return rc;
     } else {
@@ -1053,14 +1222,8 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
         for (int l = c->p.level_max; l >= c->p.level0; --l)
             if ((rc = launch_adjoint(c, aa, l))) return rc;
     } else {
-        // rebuild the tree wave by wave (tau recomputed, no segment storage),
-        // with J0 deposited for the explicit rate term
+        // rebuild the tree wave by wave (tau recomputed, no segment storage)
         if ((rc = begin_call(c, src_lum, n_src))) return rc;
-        if (det) {
-            if ((rc = zero(c, c->det, N))) return rc;
-        } else if ((rc = zero(c, c->J0, N))) {
-            return rc;
-        }
         const uint64_t ms = (uint64_t)c->o.max_sources;
         if ((rc = zero(c, c->st.created, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.split, ms * ART_MAX_LEVELS)) ||
             (rc = zero(c, c->st.exited, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.term, ms * ART_MAX_LEVELS)) ||
@@ -1071,7 +1234,7 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
         for (int s0 = 0; s0 < n_src; s0 += c->wave_max) {
             const int nw = std::min(c->wave_max, n_src - s0);
             if ((rc = seed_wave(c, s0, nw))) return rc;
-            if ((rc = sweep_wave(c, a, false))) return rc;
+            if ((rc = sweep_wave(c, a, 0))) return rc;
             for (int l = c->p.level_max; l >= c->p.level0; --l)
                 if ((rc = launch_adjoint(c, aa, l))) return rc;
         }
@@ -1080,11 +1243,9 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
     }
     const dim3 fg(fill_blocks(N)), fb(256);
     if (det)
-        hipLaunchKernelGGL((k_adj_finalize<true>), fg, fb, 0, c->stream, N, c->p.n_bins, n_H, x_n, c->p.s_H,
-                           c->p.s_d, g_rate, c->J0, c->det, c->gk, c->gdet, c->ct, g_nH, g_xn);
+        hipLaunchKernelGGL((k_adj_finalize<true>), fg, fb, 0, c->stream, N, c->gk, c->gdet, c->ct, g_nH, g_xn);
     else
-        hipLaunchKernelGGL((k_adj_finalize<false>), fg, fb, 0, c->stream, N, c->p.n_bins, n_H, x_n, c->p.s_H,
-                           c->p.s_d, g_rate, c->J0, c->det, c->gk, c->gdet, c->ct, g_nH, g_xn);
+        hipLaunchKernelGGL((k_adj_finalize<false>), fg, fb, 0, c->stream, N, c->gk, c->gdet, c->ct, g_nH, g_xn);
     HIP_TRY(hipGetLastError());
     return ART_OK;
 }

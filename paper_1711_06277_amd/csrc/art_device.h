@@ -149,7 +149,8 @@ __device__ __forceinline__ bool source_inside(const Geo& g, const double* xs) {
 }
 
 // March one ray from r_a to r_end, cell by cell.  For every segment of positive
-// length calls visit(cell, dr, dtau[], tau_in[]) with the optical depth of each
+// length calls visit(c, ijk[3], dr, dtau[], tau_in[]) (linear cell index, cell
+// coordinates, segment length) with the optical depth of each
 // bin over the segment and from the source to the segment's entry; then
 // tau[] += dtau[].  Returns kTerm as soon as tau_b > tau_term in every bin,
 // kSplit / kExit on reaching r_end.  *stuck is set if the traversal failed to
@@ -189,7 +190,7 @@ __device__ inline int march(const Geo& g, const float* __restrict__ nH, const fl
             bool thick = true;
 #pragma unroll
             for (int b = 0; b < NB; ++b) dtau[b] = kap[b] * dr;
-            visit(c, dr, dtau, tau);
+            visit(c, cell, dr, dtau, tau);
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 tau[b] += dtau[b];
@@ -222,6 +223,117 @@ __device__ inline int march(const Geo& g, const float* __restrict__ nH, const fl
     }
     *stuck = true;
     return kExit;
+}
+
+// The same traversal as march(), one segment per call, for loops that keep
+// the whole wavefront converged between segments (the forward sweep flushes
+// its deposit staging in converged code after every step).
+struct MarchState {
+    int cell[3];
+    double tnext[3];
+    double rr;
+    int it, max_steps;
+    bool alive;
+    int end;
+};
+
+__device__ inline void march_begin(const Geo& g, const Ray& r, MarchState& m) {
+    const int dims[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double p = r.xs[a] + r.r_a * r.n[a];
+        int c = (int)floor(p);
+        c = c < 0 ? 0 : (c > dims[a] - 1 ? dims[a] - 1 : c);
+        m.cell[a] = c;
+        if (r.n[a] > 0.0) m.tnext[a] = ((double)(c + 1) - r.xs[a]) * r.inv[a];
+        else if (r.n[a] < 0.0) m.tnext[a] = ((double)c - r.xs[a]) * r.inv[a];
+        else m.tnext[a] = INFINITY;
+    }
+    m.rr = r.r_a;
+    m.it = 0;
+    m.max_steps = g.nx + g.ny + g.nz + 8;
+    m.alive = true;
+    m.end = kExit;
+}
+
+// Advance one step.  Returns true if it produced a segment of positive length
+// (then c, ijk, dr, dtau[], tau_in[] describe it and tau[] already includes
+// it).  Clears m.alive and sets m.end when the ray is finished.
+template <int NB>
+__device__ inline bool march_step(const Geo& g, const float* __restrict__ nH, const float* __restrict__ xn,
+                                  const Ray& r, MarchState& m, double (&tau)[NB], bool* stuck, uint32_t& c,
+                                  int (&ijk)[3], double& dr, double (&dtau)[NB], double (&tin)[NB]) {
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    if (m.it++ >= m.max_steps) {
+        *stuck = true;
+        m.alive = false;
+        m.end = kExit;
+        return false;
+    }
+    double rb = fmin(fmin(m.tnext[0], m.tnext[1]), m.tnext[2]);
+    const bool ends = !(rb < r.r_end);
+    if (ends) rb = r.r_end;
+    dr = rb - m.rr;
+    bool seg = false;
+    if (dr > 0.0) {
+        c = ((uint32_t)m.cell[2] * (uint32_t)g.ny + (uint32_t)m.cell[1]) * (uint32_t)g.nx + (uint32_t)m.cell[0];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ijk[a] = m.cell[a];
+        const double dnH = (double)nH[c];
+        double kap[NB];
+        kap[0] = dnH * ((double)xn[c] * g.s_H + g.s_d);
+        if (NB > 1) kap[NB - 1] = dnH * g.s_d;
+        bool thick = true;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            dtau[b] = kap[b] * dr;
+            tin[b] = tau[b];
+            tau[b] += dtau[b];
+            thick = thick && (tau[b] > g.tau_term);
+        }
+        seg = true;
+        m.rr = rb;
+        if (thick) {
+            m.alive = false;
+            m.end = kTerm;
+            return true;
+        }
+    }
+    if (ends) {
+        m.alive = false;
+        m.end = r.can_split ? kSplit : kExit;
+        return seg;
+    }
+    bool moved = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (m.tnext[a] == rb) {
+            moved = true;
+            if (r.n[a] > 0.0) {
+                m.cell[a] += 1;
+                if (m.cell[a] >= dims[a]) {  // rounding guard at the boundary
+                    m.alive = false;
+                    m.end = kExit;
+                    return seg;
+                }
+                m.tnext[a] = ((double)(m.cell[a] + 1) - r.xs[a]) * r.inv[a];
+            } else {
+                m.cell[a] -= 1;
+                if (m.cell[a] < 0) {
+                    m.alive = false;
+                    m.end = kExit;
+                    return seg;
+                }
+                m.tnext[a] = ((double)m.cell[a] - r.xs[a]) * r.inv[a];
+            }
+        }
+    }
+    if (!moved) {
+        *stuck = true;
+        m.alive = false;
+        m.end = kExit;
+    }
+    return seg;
 }
 
 // (1 - e^{-x})/x and 1 - e^{-x} in FP32, accurate for small x.
