@@ -85,6 +85,7 @@ struct SrcStats {
 
 struct SweepArgs {
     Geo g;
+    const float2* q;   // (n_H, x_n) per cell, packed once per call
     const float* nH;
     const float* xn;
     const double* src_pos;
@@ -147,6 +148,13 @@ __global__ void k_fill_f64(double* p, uint64_t n) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = 0.0;
+}
+
+// Interleave (n_H, x_n) so that the sweep gathers one 8-byte word per segment.
+__global__ void k_pack(uint64_t N, const float* nH, const float* xn, float2* q) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        q[i] = make_float2(nH[i], xn[i]);
 }
 
 // Reset the call counters; in deterministic mode also set the fixed-point
@@ -268,13 +276,12 @@ struct Deposit {
     using V = typename std::conditional<DET, unsigned long long, float>::type;
     static constexpr int S = 256;          // cache slots
     static constexpr int CAP = 128;        // staging capacity (>= 64 + flush threshold)
-    static constexpr int LPE = NV <= 4 ? 4 : 8;  // lanes per staged cell = AoS stride
-    volatile ART_LDS uint32_t* keys;       // [S]
-    volatile ART_LDS uint8_t* own;         // [S]
-    ART_LDS V* vals;                       // [NV][S]
-    volatile ART_LDS uint32_t* n_staged;   // [1]
+    static constexpr int LPE = NV <= 4 ? 4 : 8;  // values per cell slot = AoS stride = lanes per staged cell
+    ART_LDS uint32_t* keys;                // [S]
+    ART_LDS V* vals;                       // [S][LPE]  (a slot's values contiguous)
     ART_LDS uint32_t* skey;                // [CAP]
-    ART_LDS V* sval;                       // [NV][CAP]
+    ART_LDS V* sval;                       // [CAP][LPE]
+    uint32_t n_staged;                     // wave-uniform
 
     __device__ static inline uint32_t slot(const int (&ijk)[3]) {
         return (uint32_t)((ijk[0] & 7) | ((ijk[1] & 7) << 3) | ((ijk[2] & 3) << 6));
@@ -286,58 +293,86 @@ struct Deposit {
         __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
 
+    // Compiler-only barrier: LDS operations of different lanes in different
+    // branches are not reordered across it.
+    __device__ static inline void lds_order() { __asm__ volatile("" ::: "memory"); }
+
     __device__ inline void init(int lane) {
         for (int s = lane; s < S; s += kWave) keys[s] = kEmptyKey;
-        if (lane == 0) *n_staged = 0u;
+        n_staged = 0u;
+        lds_order();
     }
 
-    __device__ inline void stage(uint32_t c, const V (&v)[NV]) {
-        const uint32_t e = __hip_atomic_fetch_add((ART_LDS uint32_t*)n_staged, 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_WAVEFRONT);
-        skey[e] = c;
-#pragma unroll
-        for (int q = 0; q < NV; ++q) sval[q * CAP + e] = v[q];
-    }
-
-    // Active lanes only (any subset of the wavefront).
-    __device__ inline void deposit(uint32_t c, const int (&ijk)[3], const V (&v)[NV], int lane) {
+    // Active lanes only (any subset of the wavefront).  A lane whose cell hits
+    // the slot's key adds into LDS.  Otherwise it tries to swap its cell into
+    // the slot (LDS compare-and-swap: of several lanes one wins); the winner
+    // hands back the slot's previous cell and values, to be staged for global
+    // memory, and initialises the slot with its own values; lanes that lost to
+    // a lane with the same cell add after that; any other lane hands back its
+    // own deposit.  Returns true if (pk, pv) must be staged.
+    __device__ inline bool deposit(uint32_t c, const int (&ijk)[3], const V (&v)[NV], uint32_t& pk, V (&pv)[NV]) {
         const uint32_t h = slot(ijk);
+        ART_LDS V* sv = vals + h * LPE;
         const uint32_t key0 = keys[h];
         const bool hit = key0 == c;
         if (hit) {
 #pragma unroll
-            for (int q = 0; q < NV; ++q) lds_add(&vals[q * S + h], v[q]);
+            for (int q = 0; q < NV; ++q) lds_add(&sv[q], v[q]);
         }
-        bool claimed = false, owner = false;
-        if (!hit) {
-            keys[h] = c;
-            claimed = keys[h] == c;
-        }
-        if (claimed) {
-            own[h] = (uint8_t)lane;
-            owner = own[h] == (uint8_t)lane;
-        }
-        if (owner) {
-            if (key0 != kEmptyKey) {
-                V old[NV];
+        // Lanes that hit and lanes that evict run mutually exclusive branches,
+        // so nothing orders them for the compiler: keep every add issued before
+        // any eviction (LDS then executes them in issue order).
+        lds_order();
+        bool pend = false;
+        uint32_t prev = key0;
+        if (!hit) prev = atomicCAS((uint32_t*)&keys[h], key0, c);
+        const bool won = !hit && prev == key0;
+        if (won) {  // won the slot: evict the previous cell, initialise with ours
+            pk = key0;
+            pend = key0 != kEmptyKey;
 #pragma unroll
-                for (int q = 0; q < NV; ++q) old[q] = vals[q * S + h];
-                stage(key0, old);
-            }
+            for (int q = 0; q < NV; ++q) pv[q] = sv[q];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) vals[q * S + h] = v[q];
+            for (int q = 0; q < NV; ++q) sv[q] = v[q];
         }
-        if (claimed && !owner) {
+        // lanes that lost the slot to a lane with the same cell add after the
+        // winner has initialised it
+        lds_order();
+        const bool follower = !hit && !won && prev == c;
+        if (follower) {
 #pragma unroll
-            for (int q = 0; q < NV; ++q) lds_add(&vals[q * S + h], v[q]);
+            for (int q = 0; q < NV; ++q) lds_add(&sv[q], v[q]);
         }
-        if (!hit && !claimed) stage(c, v);
+        if (!hit && !won && !follower) {
+            pk = c;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) pv[q] = v[q];
+            pend = true;
+        }
+        lds_order();
+        return pend;
+    }
+
+    // Converged: append the lanes' pending entries to the staging list.
+    __device__ inline void stage(bool pend, uint32_t pk, const V (&pv)[NV]) {
+        const unsigned long long mk = __ballot(pend);
+        lds_order();
+        if (pend) {
+            const uint32_t e = n_staged + (uint32_t)__builtin_amdgcn_mbcnt_hi(
+                                              (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+            skey[e] = pk;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) sval[e * LPE + q] = pv[q];
+        }
+        n_staged += (uint32_t)__popcll(mk);
+        lds_order();
     }
 
     // Converged: the whole wavefront writes the staged cells to the AoS
-    // accumulator (stride LPE) when at least `threshold` are staged.
+    // accumulator (stride LPE) when at least `threshold` are staged: lane l adds
+    // value (l mod LPE) of staged cell (l / LPE).
     __device__ inline void flush(V* acc, int lane, uint32_t threshold) {
-        const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)*n_staged);
+        const uint32_t n = n_staged;
         if (n < threshold || n == 0) return;
         const uint32_t per = kWave / LPE;
         const int f = lane % LPE;
@@ -345,12 +380,13 @@ struct Deposit {
             const uint32_t e = b0 + (uint32_t)lane / LPE;
             if (e < n && f < NV) {
                 V* p = acc + (uint64_t)skey[e] * LPE + f;
-                const V x = sval[f * CAP + e];
+                const V x = sval[e * LPE + f];
                 if (DET) atomicAdd((unsigned long long*)p, (unsigned long long)x);
                 else unsafeAtomicAdd((float*)p, (float)x);
             }
         }
-        if (lane == 0) *n_staged = 0u;
+        n_staged = 0u;
+        lds_order();
     }
 
     // Converged: empty the cache into the accumulator.
@@ -358,13 +394,12 @@ struct Deposit {
         for (int s0 = 0; s0 < S; s0 += kWave) {
             const int s = s0 + lane;
             const uint32_t k = keys[s];
-            if (k != kEmptyKey) {
-                V old[NV];
+            V old[NV];
 #pragma unroll
-                for (int q = 0; q < NV; ++q) old[q] = vals[q * S + s];
-                stage(k, old);
-                keys[s] = kEmptyKey;
-            }
+            for (int q = 0; q < NV; ++q) old[q] = vals[s * LPE + q];
+            stage(k != kEmptyKey, k, old);
+            keys[s] = kEmptyKey;
+            lds_order();
             flush(acc, lane, 1u);
         }
     }
@@ -390,11 +425,9 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
     constexpr int SS = MODE ? Dep::S : 1;
     constexpr int SC = MODE ? Dep::CAP : 1;
     __shared__ uint32_t sh_keys[NW][SS];
-    __shared__ uint8_t sh_own[NW][SS];
-    __shared__ V sh_vals[NW][NV * SS];
-    __shared__ uint32_t sh_n[NW];
+    __shared__ V sh_vals[NW][Dep::LPE * SS];
     __shared__ uint32_t sh_skey[NW][SC];
-    __shared__ V sh_sval[NW][NV * SC];
+    __shared__ V sh_sval[NW][Dep::LPE * SC];
     const Geo& g = a.g;
     Counters* ct = a.ct;
     const int lane = lane_id();
@@ -412,9 +445,9 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
     const unsigned long long dweight = 1ull << (2 * (g.level_max - level));
     V* acc = (V*)(DET ? (void*)a.det : (void*)a.acc);
 
-    const int w = (int)(threadIdx.x >> 6);
-    Dep dep{(volatile ART_LDS uint32_t*)sh_keys[w], (volatile ART_LDS uint8_t*)sh_own[w], (ART_LDS V*)sh_vals[w],
-            (volatile ART_LDS uint32_t*)&sh_n[w], (ART_LDS uint32_t*)sh_skey[w], (ART_LDS V*)sh_sval[w]};
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    Dep dep{(ART_LDS uint32_t*)sh_keys[w], (ART_LDS V*)sh_vals[w], (ART_LDS uint32_t*)sh_skey[w],
+            (ART_LDS V*)sh_sval[w], 0u};
     if (MODE) dep.init(lane);
     auto quant = [&](float x) -> V {
         if (DET) return (V)(unsigned long long)__double2ll_rn((double)x * scale);
@@ -462,17 +495,22 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
 #pragma unroll
             for (int b = 0; b < NB; ++b) lnom[b] = a.src_lum[(uint64_t)src * NB + b] * lnom_scale;
             if (bad_src || !source_inside(g, r.xs)) bad_src = true;
-            else if (!r.starts_outside) march_begin(g, r, m);
+            else if (!r.starts_outside) march_begin(g, a.q, r, m);
         }
         // converged march: one segment per lane per iteration
+        const float nxf = (float)r.n[0], nyf = (float)r.n[1], nzf = (float)r.n[2];
         while (__ballot(m.alive)) {
-            if (m.alive) {
+            bool pend = false;
+            uint32_t pk = 0;
+            V pv[NV];
+            {
                 uint32_t c;
                 int ijk[3];
                 double dr, dtau[NB], tin[NB];
-                if (march_step<NB>(g, a.nH, a.xn, r, m, tau, &stuck, c, ijk, dr, dtau, tin)) {
+                if (march_step<NB>(g, a.q, r, m, tau, &stuck, c, ijk, dr, dtau, tin)) {
                     ++nseg;
                     if (MODE) {
+#pragma clang fp contract(fast)
                         const float drf = (float)dr;
                         float dLs = 0.0f, j0 = 0.0f, j1 = 0.0f;
 #pragma unroll
@@ -487,15 +525,18 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
                         }
                         V v[NV];
                         v[0] = quant(j0);
-                        v[1] = quant((float)r.n[0] * dLs);
-                        v[2] = quant((float)r.n[1] * dLs);
-                        v[3] = quant((float)r.n[2] * dLs);
+                        v[1] = quant(nxf * dLs);
+                        v[2] = quant(nyf * dLs);
+                        v[3] = quant(nzf * dLs);
                         if (NV > 4) v[4 % NV] = quant(j1);
-                        dep.deposit(c, ijk, v, lane);
+                        pend = dep.deposit(c, ijk, v, pk, pv);
                     }
                 }
             }
-            if (MODE) dep.flush(acc, lane, 64u);
+            if (MODE) {
+                dep.stage(pend, pk, pv);
+                dep.flush(acc, lane, 64u);
+            }
         }
         const int end = m.end;
         if (active && end != kSplit) {
@@ -792,6 +833,7 @@ struct art_ctx {
     double* gk;
     unsigned long long* gdet;
     float* fscratch;
+    float2* q;                // [N] packed (n_H, x_n)
     // tape of the last forward (valid only for a single-wave trace)
     const void* tape_key[4];
     int tape_nsrc;
@@ -908,6 +950,7 @@ void free_all(art_ctx* c) {
     (void)hipFree(c->gk);
     (void)hipFree(c->gdet);
     (void)hipFree(c->fscratch);
+    (void)hipFree(c->q);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->ev_call0) (void)hipEventDestroy(c->ev_call0);
     if (c->ev_call1) (void)hipEventDestroy(c->ev_call1);
@@ -924,6 +967,7 @@ SweepArgs sweep_args(art_ctx* c, const float* nH, const float* xn, const double*
                      float* force, float* J, int n_src) {
     SweepArgs a;
     a.g = c->geo;
+    a.q = c->q;
     a.nH = nH;
     a.xn = xn;
     a.src_pos = pos;
@@ -998,8 +1042,10 @@ int sweep_wave(art_ctx* c, const SweepArgs& a, int mode) {
     return ART_OK;
 }
 
-int begin_call(art_ctx* c, const float* lum, int n_src) {
+int begin_call(art_ctx* c, const float* lum, int n_src, const float* nH, const float* xn) {
     hipLaunchKernelGGL(k_begin_call, dim3(1), dim3(256), 0, c->stream, c->ct, lum, n_src * c->p.n_bins);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_pack, dim3(fill_blocks(c->N)), dim3(256), 0, c->stream, c->N, nH, xn, c->q);
     HIP_TRY(hipGetLastError());
     return ART_OK;
 }
@@ -1104,6 +1150,7 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
     if (ok && o.enable_adjoint)
         ok = dmalloc(&c->pool.child, cap) && dmalloc(&c->pool.G, 2 * cap);
     if (ok) ok = det ? dmalloc(&c->det, 8 * N) : dmalloc(&c->acc, 8 * N);
+    if (ok) ok = dmalloc(&c->q, N);
     if (ok && o.enable_adjoint) ok = det ? dmalloc(&c->gdet, 2 * N) : dmalloc(&c->gk, 2 * N);
     if (ok) {
         c->ev.resize(2 * (ART_MAX_LEVELS + 1) * 64);
@@ -1138,7 +1185,7 @@ int art_trace(art_ctx* c, const float* n_H, const float* x_n, const double* src_
     c->tape_ok = false;
     if (c->timing) HIP_TRY(hipEventRecord(c->ev_call0, c->stream));
     int rc;
-    if ((rc = begin_call(c, src_lum, n_src))) return rc;
+    if ((rc = begin_call(c, src_lum, n_src, n_H, x_n))) return rc;
     const int mode = (J && c->p.n_bins > 1) ? 2 : 1;
     const int lpe = mode == 2 ? 8 : 4;
     if (det) {
@@ -1223,7 +1270,7 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
             if ((rc = launch_adjoint(c, aa, l))) return rc;
     } else {
         // rebuild the tree wave by wave (tau recomputed, no segment storage)
-        if ((rc = begin_call(c, src_lum, n_src))) return rc;
+        if ((rc = begin_call(c, src_lum, n_src, n_H, x_n))) return rc;
         const uint64_t ms = (uint64_t)c->o.max_sources;
         if ((rc = zero(c, c->st.created, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.split, ms * ART_MAX_LEVELS)) ||
             (rc = zero(c, c->st.exited, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.term, ms * ART_MAX_LEVELS)) ||

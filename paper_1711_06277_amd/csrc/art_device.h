@@ -227,17 +227,25 @@ __device__ inline int march(const Geo& g, const float* __restrict__ nH, const fl
 
 // The same traversal as march(), one segment per call, for loops that keep
 // the whole wavefront converged between segments (the forward sweep flushes
-// its deposit staging in converged code after every step).
+// its deposit staging in converged code after every step).  The (n_H, x_n)
+// pair of the next cell is loaded as soon as the ray steps into it, so the
+// gather's latency overlaps the current segment's deposit.
 struct MarchState {
     int cell[3];
     double tnext[3];
     double rr;
+    uint32_t c;       // linear index of the current cell
+    float2 q;         // (n_H, x_n) of the current cell
     int it, max_steps;
     bool alive;
     int end;
 };
 
-__device__ inline void march_begin(const Geo& g, const Ray& r, MarchState& m) {
+__device__ __forceinline__ uint32_t cell_index(const Geo& g, const int (&cell)[3]) {
+    return ((uint32_t)cell[2] * (uint32_t)g.ny + (uint32_t)cell[1]) * (uint32_t)g.nx + (uint32_t)cell[0];
+}
+
+__device__ inline void march_begin(const Geo& g, const float2* __restrict__ q, const Ray& r, MarchState& m) {
     const int dims[3] = {g.nx, g.ny, g.nz};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -250,101 +258,94 @@ __device__ inline void march_begin(const Geo& g, const Ray& r, MarchState& m) {
         else m.tnext[a] = INFINITY;
     }
     m.rr = r.r_a;
+    m.c = cell_index(g, m.cell);
+    m.q = q[m.c];
     m.it = 0;
     m.max_steps = g.nx + g.ny + g.nz + 8;
     m.alive = true;
     m.end = kExit;
 }
 
-// Advance one step.  Returns true if it produced a segment of positive length
+// Advance one step, branch-free: every lane computes the candidate step and
+// commits it only if it is alive, so the wavefront never splits around the
+// march state.  Returns true if the lane produced a segment of positive length
 // (then c, ijk, dr, dtau[], tau_in[] describe it and tau[] already includes
 // it).  Clears m.alive and sets m.end when the ray is finished.
 template <int NB>
-__device__ inline bool march_step(const Geo& g, const float* __restrict__ nH, const float* __restrict__ xn,
-                                  const Ray& r, MarchState& m, double (&tau)[NB], bool* stuck, uint32_t& c,
-                                  int (&ijk)[3], double& dr, double (&dtau)[NB], double (&tin)[NB]) {
+__device__ __forceinline__ bool march_step(const Geo& g, const float2* __restrict__ q, const Ray& r,
+                                           MarchState& m, double (&tau)[NB], bool* stuck, uint32_t& c,
+                                           int (&ijk)[3], double& dr, double (&dtau)[NB], double (&tin)[NB]) {
     const int dims[3] = {g.nx, g.ny, g.nz};
-    if (m.it++ >= m.max_steps) {
-        *stuck = true;
-        m.alive = false;
-        m.end = kExit;
-        return false;
-    }
-    double rb = fmin(fmin(m.tnext[0], m.tnext[1]), m.tnext[2]);
-    const bool ends = !(rb < r.r_end);
-    if (ends) rb = r.r_end;
+    const bool alive = m.alive;
+    const bool budget = m.it < m.max_steps;
+    m.it += 1;
+    const double rb0 = fmin(fmin(m.tnext[0], m.tnext[1]), m.tnext[2]);
+    const bool ends = !(rb0 < r.r_end);
+    const double rb = ends ? r.r_end : rb0;
     dr = rb - m.rr;
-    bool seg = false;
-    if (dr > 0.0) {
-        c = ((uint32_t)m.cell[2] * (uint32_t)g.ny + (uint32_t)m.cell[1]) * (uint32_t)g.nx + (uint32_t)m.cell[0];
+    const bool seg = alive && budget && dr > 0.0;
+    c = m.c;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) ijk[a] = m.cell[a];
-        const double dnH = (double)nH[c];
-        double kap[NB];
-        kap[0] = dnH * ((double)xn[c] * g.s_H + g.s_d);
-        if (NB > 1) kap[NB - 1] = dnH * g.s_d;
-        bool thick = true;
+    for (int a = 0; a < 3; ++a) ijk[a] = m.cell[a];
+    const double dnH = (double)m.q.x;
+    double kap[NB];
+    kap[0] = dnH * ((double)m.q.y * g.s_H + g.s_d);
+    if (NB > 1) kap[NB - 1] = dnH * g.s_d;
+    bool thick = seg;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            dtau[b] = kap[b] * dr;
-            tin[b] = tau[b];
-            tau[b] += dtau[b];
-            thick = thick && (tau[b] > g.tau_term);
-        }
-        seg = true;
-        m.rr = rb;
-        if (thick) {
-            m.alive = false;
-            m.end = kTerm;
-            return true;
-        }
+    for (int b = 0; b < NB; ++b) {
+        dtau[b] = kap[b] * dr;
+        tin[b] = tau[b];
+        const double t1 = tau[b] + dtau[b];
+        tau[b] = seg ? t1 : tau[b];
+        thick = thick && (t1 > g.tau_term);
     }
-    if (ends) {
-        m.alive = false;
-        m.end = r.can_split ? kSplit : kExit;
-        return seg;
-    }
-    bool moved = false;
+    m.rr = seg ? rb : m.rr;
+    // step every axis whose face is at rb (ties step together)
+    const bool go = alive && budget && !ends && !thick;
+    bool moved = false, out = false;
+    int nc[3];
+    double nt[3];
+    bool st[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (m.tnext[a] == rb) {
-            moved = true;
-            if (r.n[a] > 0.0) {
-                m.cell[a] += 1;
-                if (m.cell[a] >= dims[a]) {  // rounding guard at the boundary
-                    m.alive = false;
-                    m.end = kExit;
-                    return seg;
-                }
-                m.tnext[a] = ((double)(m.cell[a] + 1) - r.xs[a]) * r.inv[a];
-            } else {
-                m.cell[a] -= 1;
-                if (m.cell[a] < 0) {
-                    m.alive = false;
-                    m.end = kExit;
-                    return seg;
-                }
-                m.tnext[a] = ((double)m.cell[a] - r.xs[a]) * r.inv[a];
-            }
-        }
+        st[a] = m.tnext[a] == rb;
+        const bool up = r.n[a] > 0.0;
+        nc[a] = m.cell[a] + (up ? 1 : -1);
+        const double face = (double)(up ? nc[a] + 1 : nc[a]);
+        nt[a] = (face - r.xs[a]) * r.inv[a];
+        moved = moved || st[a];
+        out = out || (st[a] && (nc[a] < 0 || nc[a] >= dims[a]));  // rounding guard at the boundary
     }
-    if (!moved) {
-        *stuck = true;
-        m.alive = false;
-        m.end = kExit;
+    const bool adv = go && moved && !out;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool s2 = adv && st[a];
+        m.cell[a] = s2 ? nc[a] : m.cell[a];
+        m.tnext[a] = s2 ? nt[a] : m.tnext[a];
+    }
+    const bool bad = alive && (!budget || (go && !moved));
+    *stuck = *stuck || bad;
+    const bool finish = alive && !adv;
+    const int end_new = thick ? kTerm : ((ends && r.can_split) ? kSplit : kExit);
+    m.end = finish ? end_new : m.end;
+    m.alive = alive && adv;
+    if (adv) {
+        m.c = cell_index(g, m.cell);
+        m.q = q[m.c];  // prefetch for the next step
     }
     return seg;
 }
 
-// (1 - e^{-x})/x and 1 - e^{-x} in FP32, accurate for small x.
+// (1 - e^{-x})/x and 1 - e^{-x} in FP32, accurate for small x (series below
+// 0.1, where 1 - e^{-x} would cancel), branch-free.
 __device__ __forceinline__ void absorb_factors(float x, float& phi, float& one_minus_e) {
-    if (x < 0.1f) {
-        phi = 1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f))));
-        one_minus_e = x * phi;
-    } else {
-        one_minus_e = 1.0f - __expf(-x);
-        phi = one_minus_e / x;
-    }
+#pragma clang fp contract(fast)
+    const float ser = 1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f))));
+    const float ome = 1.0f - __expf(-x);
+    const bool small = x < 0.1f;
+    phi = small ? ser : ome * __builtin_amdgcn_rcpf(x);
+    one_minus_e = small ? x * ser : ome;
 }
 
 // FP64 versions for the adjoint: phi(x) = (1 - e^{-x})/x given om = 1 - e^{-x},
