@@ -1,0 +1,84 @@
+"""The forward + adjoint sweep captured in one HIP graph (through torch's graph
+capture on the library's stream) and replayed several times, with eager work
+and synchronisations between replays: every replay must equal the eager result
+(bitwise in the deterministic mode)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1711_06277_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(n=40, n_src=6):
+    wl = I.config(4, n_src=n_src, n=n)
+    return wl
+
+
+def _tensors(wl):
+    d = "cuda"
+    return (torch.from_numpy(wl.n_H).to(d), torch.from_numpy(wl.x_n).to(d),
+            torch.from_numpy(wl.src_pos).to(d), torch.from_numpy(wl.src_lum).to(d),
+            torch.from_numpy(wl.w).to(d), torch.from_numpy(wl.v).to(d))
+
+
+@pytest.mark.parametrize("deterministic,pool_rays", [(True, 0), (False, 0), (True, 300000)])
+def test_graph_replay_matches_eager(deterministic, pool_rays):
+    from paper_1711_06277_amd.api import ArtTracer
+    wl = _problem()
+    nH, xn, pos, lum, w, v = _tensors(wl)
+    tr = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
+                   deterministic=deterministic, max_sources=wl.n_src, enable_adjoint=True,
+                   pool_rays=pool_rays)
+    try:
+        N = wl.n_cells
+        outs = [torch.empty(N, device="cuda"), torch.empty((3, N), device="cuda"),
+                torch.empty(N, device="cuda"), torch.empty(N, device="cuda")]
+
+        def step():
+            tr.trace(nH, xn, pos, lum, out=(outs[0], outs[1], None), check=False)
+            tr.adjoint(nH, xn, pos, lum, w, v, out=(outs[2], outs[3]), check=False)
+
+        # eager reference
+        step()
+        torch.cuda.synchronize()
+        assert tr.sync() == 0
+        ref = [o.clone() for o in outs]
+        if pool_rays:
+            assert tr.stats(wl.n_src).n_waves > 1
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()  # warm-up on the capture stream
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        for rep in range(3):
+            for o in outs:
+                o.fill_(-1.0)
+            g.replay()
+            torch.cuda.synchronize()
+            assert tr.sync() == 0
+            for name, a, b in zip(("rate", "force", "g_nH", "g_xn"), outs, ref):
+                if deterministic:
+                    assert torch.equal(a, b), f"replay {rep}: {name} differs from eager"
+                elif name == "force":
+                    # FP32 atomics add in a different order on every run; a
+                    # component can cancel, so compare the vector per cell
+                    d = (a - b).norm(dim=0)
+                    f = b.norm(dim=0)
+                    assert (d <= 1e-4 * f + 1e-6 * float(f.max())).all(), f"replay {rep}: force"
+                else:
+                    m = b.abs() > 1e-8 * float(b.abs().max())
+                    rel = ((a - b).abs()[m] / b.abs()[m]).max().item()
+                    assert rel < 1e-4, f"replay {rep}: {name} rel diff {rel}"
+            # eager work between replays
+            x = torch.randn(1 << 20, device="cuda")
+            (x * 2).sum().item()
+        del g
+    finally:
+        tr.close()

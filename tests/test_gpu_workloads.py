@@ -1,0 +1,144 @@
+"""Parity at the benchmark workloads' full sizes, in the launch configuration the
+benchmark uses (all sources of a workload in one batched call).
+
+The FP64 oracle cannot trace 64 sources at 256^3 (or 1024 at 512^3) in test
+time, so these tests compare what it can compute one by one (the ray tree and
+the escaped / residual luminosity of sampled sources) and properties that hold
+at any size: photon conservation, the destroy-counter total, linearity in the
+sources (batched == sum of one-source calls), and bitwise determinism.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1711_06277_amd import inputs as I
+from tests.gpu_common import CONS_TOL, compare_cells, conservation, kappas
+
+pytestmark = pytest.mark.gpu
+
+
+def tracer(wl, **kw):
+    from paper_1711_06277_amd.api import ArtTracer
+    return ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
+                     level0=wl.level0, level_max=wl.level_max, phi_c=wl.phi_c,
+                     tau_term=wl.tau_term, **kw)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def test_workload3_batched_full_size(oracle):
+    """256^3, 64 sources, 2 bins: per-source trees of sampled sources match the
+    oracle bit for bit; batched equals the sum of one-source calls; photon
+    conservation holds for the whole batch."""
+    wl = I.config(3)
+    tr = tracer(wl, max_sources=wl.n_src)
+    nH, xn, pos, lum = dev(wl.n_H), dev(wl.x_n), dev(wl.src_pos), dev(wl.src_lum)
+    try:
+        rate, force, J = tr.trace(nH, xn, pos, lum, want_J=True)
+        st = tr.stats(wl.n_src)
+        assert st.status == 0 and st.n_waves == 1
+        assert st.destroy == st.destroy_expected == 64 * 12 * 4 ** 13
+        cons = conservation(wl, J.cpu().numpy(), st)
+        assert max(cons) <= CONS_TOL, cons
+        for s in (0, 37):
+            ref = oracle.trace_workload(wl.subset([s]))
+            for key, mine in (("created", st.src_created), ("split", st.src_split),
+                              ("exited", st.src_exited), ("terminated", st.src_terminated)):
+                assert np.array_equal(mine[s], ref.__dict__[key][0]), (s, key)
+            np.testing.assert_allclose(st.src_escaped[s], ref.escaped[0], rtol=1e-5,
+                                       atol=1e-12 * float(lum.sum()))
+            np.testing.assert_allclose(st.src_residual[s], ref.residual[0], rtol=1e-4,
+                                       atol=1e-12 * float(lum.sum()))
+            assert abs(int(st.src_segments[s]) / int(ref.segments[0]) - 1) < 1e-4
+        rate_b, force_b = rate.clone(), force.clone()
+    finally:
+        tr.close()
+    tp = tracer(wl, max_sources=1)
+    try:
+        acc_r = torch.zeros_like(rate_b)
+        acc_f = torch.zeros_like(force_b)
+        for s in range(wl.n_src):
+            r1, f1 = tp.trace(nH, xn, pos[s:s + 1], lum[s:s + 1])
+            acc_r += r1
+            acc_f += f1
+    finally:
+        tp.close()
+    L = float(wl.src_lum.astype(np.float64).sum())
+    compare_cells("batched vs plain rate", rate_b.cpu().numpy(), acc_r.cpu().numpy().astype(np.float64), L)
+
+
+def test_workload4_adjoint_full_size(oracle):
+    """128^3, sigmoid x_n, 8 sources: GPU adjoint vs the FP64 oracle adjoint."""
+    wl = I.config(4)
+    ref_nH, ref_xn = oracle.adjoint(wl.nx, wl.ny, wl.nz, wl.n_H, wl.x_n, wl.src_pos, wl.src_lum,
+                                    wl.w, wl.v, **wl.params())
+    tr = tracer(wl, max_sources=wl.n_src, enable_adjoint=True)
+    try:
+        args = (dev(wl.n_H), dev(wl.x_n), dev(wl.src_pos), dev(wl.src_lum))
+        tr.trace(*args)
+        g_nH, g_xn = tr.adjoint(*args, dev(wl.w), dev(wl.v))
+    finally:
+        tr.close()
+    for name, gpu, ref in (("g_nH", g_nH, ref_nH), ("g_xn", g_xn, ref_xn)):
+        gpu = gpu.cpu().numpy().astype(np.float64)
+        m = np.abs(ref) > 1e-6 * np.abs(ref).max()
+        err = np.abs(gpu[m] - ref[m]) / np.abs(ref[m])
+        assert err.max() <= 1e-4, f"{name}: {err.max():.3e}"
+
+
+def test_workload5_full_grid_deterministic_graph():
+    """512^3 std-2 field, a 32-source sample of the 1024 (dN/dL ~ L^-2), two bins,
+    deterministic deposits, forward + adjoint captured in one HIP graph: two
+    replays are bitwise equal, the destroy count is complete, photons are
+    conserved, and splitting the batch in two halves gives the same rate."""
+    full = I.config(5)
+    wl = full.subset(np.arange(0, 1024, 32))
+    tr = tracer(wl, max_sources=wl.n_src, enable_adjoint=True, deterministic=True)
+    nH, xn, pos, lum = dev(wl.n_H), dev(wl.x_n), dev(wl.src_pos), dev(wl.src_lum)
+    w, v = dev(wl.w), dev(wl.v)
+    N = wl.n_cells
+    try:
+        outs = [torch.empty(N, device="cuda"), torch.empty((3, N), device="cuda"),
+                torch.empty((2, N), device="cuda"), torch.empty(N, device="cuda"),
+                torch.empty(N, device="cuda")]
+
+        def step():
+            tr.trace(nH, xn, pos, lum, want_J=True, out=(outs[0], outs[1], outs[2]), check=False)
+            tr.adjoint(nH, xn, pos, lum, w, v, out=(outs[3], outs[4]), check=False)
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        assert tr.sync() == 0
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        g.replay()
+        torch.cuda.synchronize()
+        first = [o.clone() for o in outs]
+        g.replay()
+        torch.cuda.synchronize()
+        assert tr.sync() == 0
+        for a, b in zip(outs, first):
+            assert torch.equal(a, b)
+        st = tr.stats(wl.n_src)
+        assert st.destroy == st.destroy_expected
+        cons = conservation(wl, outs[2].cpu().numpy(), st)
+        assert max(cons) <= CONS_TOL, cons
+        assert torch.isfinite(outs[3]).all() and torch.isfinite(outs[4]).all()
+        rate_all = outs[0].clone()
+        half = wl.n_src // 2
+        r1, _ = tr.trace(nH, xn, pos[:half], lum[:half])
+        r1 = r1.clone()
+        r2, _ = tr.trace(nH, xn, pos[half:], lum[half:])
+        del g
+    finally:
+        tr.close()
+    L = float(wl.src_lum.astype(np.float64).sum())
+    compare_cells("halves", (r1 + r2).cpu().numpy(), rate_all.cpu().numpy().astype(np.float64), L,
+                  rel=1e-5)
