@@ -29,6 +29,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_1711_06277_amd/csrc/art.hip", "paper_1711_06277_amd/csrc/art_device.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: int):
+    """HBM bytes per trace from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (copy-calibrated), or None if the kernel has changed since."""
+    if workload != 3:
+        return None
+    path = os.path.join(ROOT, "profiles", "k_sweep_c3_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_trace", "kernel_sources_sha"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources_sha") != kernel_sources_sha():
+        return None
+    return float(vals["traffic_bytes_per_trace"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +203,7 @@ def main():
         log(f"[bench] oracle: {seg_cpu / dt:.3e} segments/s on one core ({dt:.1f} s)")
 
     tr.close()
+    traffic = measured_traffic(args.workload) if not wl.deterministic else None
     result = {
         "metric": "ray-cell segments/s (batched, one full trace of all sources per step)",
         "value": seg_per_s,
@@ -197,7 +226,10 @@ def main():
                    "segments_per_trace": segments, "waves": st.n_waves},
         "plain": plain,
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
+                     "traffic": None if traffic is None else traffic / 1e9,
+                     "traffic_unit": "GB per trace (sum over the per-level k_sweep launches), "
+                                     "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated",
                      "kernel": "k_sweep (one launch per HEALPix level)",
                      "bytes_per_segment": BYTES_PER_SEGMENT,
                      "sweep_ms_per_step": sweep_ms / args.steps,
