@@ -22,7 +22,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
-BYTES_PER_SEGMENT = 40         # 2 x 4 B gather (n_H, x_n) + 4 FP32 read-modify-writes (J_i, F_xyz)
+# algorithmic bytes per ray-cell segment: the (n_H, x_n) gather (8 B) and a
+# read-modify-write of the cell's four FP32 outputs (J_i, F_x, F_y, F_z).  The
+# fixed-point mode's 8-byte accumulators would count 72 B; the roofline uses the
+# method's 40 B in both modes.
+BYTES_PER_SEGMENT = 40
+BYTES_PER_SEGMENT_FIXED_POINT = 72
 
 
 def log(*a):
@@ -38,12 +43,13 @@ def kernel_sources_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: int):
+def measured_traffic(workload: int, deterministic: bool):
     """HBM bytes per trace from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary (copy-calibrated), or None if the kernel has changed since."""
     if workload != 3:
         return None
-    path = os.path.join(ROOT, "profiles", "k_sweep_c3_traffic.md")
+    name = "k_sweep_c3_traffic.md" if deterministic else "k_sweep_c3_atomic_traffic.md"
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -65,9 +71,12 @@ def main():
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--no-plain", action="store_true", help="skip the one-source-per-call timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--deterministic", action="store_true")
+    ap.add_argument("--atomic", action="store_true",
+                    help="FP32 atomic deposits instead of the (faster) 64-bit fixed-point ones")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the sweep's launch shape with art_autotune before timing")
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     args = ap.parse_args()
@@ -89,8 +98,9 @@ def main():
 
     t0 = time.time()
     wl = I.config(args.workload)
-    if args.deterministic:
-        wl.deterministic = True
+    # 64-bit fixed-point deposits: integer LDS and global atomics are faster than
+    # FP32 ones on this GPU, and the sums are bitwise reproducible
+    wl.deterministic = not args.atomic
     log(f"[bench] workload {wl.name}: generated in {time.time() - t0:.1f}s")
 
     tr = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
@@ -106,6 +116,10 @@ def main():
     rate = torch.empty(N, dtype=torch.float32, device=dev)
     force = torch.empty((3, N), dtype=torch.float32, device=dev)
     out = (rate, force, None)
+
+    if args.autotune:
+        bb, bp, ms = tr.autotune(nH, xn, pos, lum)
+        log(f"[bench] autotune: {bb} threads x {bp} workgroups per CU ({ms:.1f} ms)")
 
     # ---- batched: all sources in one call ----
     for _ in range(args.warmup):
@@ -144,7 +158,8 @@ def main():
 
     # roofline of the sweep kernel: algorithmic bytes / summed kernel time
     sweep_s = sweep_ms / 1e3
-    achieved_gbs = segments * args.steps * BYTES_PER_SEGMENT / sweep_s / 1e9
+    bps = BYTES_PER_SEGMENT
+    achieved_gbs = segments * args.steps * bps / sweep_s / 1e9
     avg_launch_ms = sweep_ms / max(1, sweep_launches)
 
     # ---- plain: one source per call, same kernel and parameters ----
@@ -203,7 +218,7 @@ def main():
         log(f"[bench] oracle: {seg_cpu / dt:.3e} segments/s on one core ({dt:.1f} s)")
 
     tr.close()
-    traffic = measured_traffic(args.workload) if not wl.deterministic else None
+    traffic = measured_traffic(args.workload, wl.deterministic)
     result = {
         "metric": "ray-cell segments/s (batched, one full trace of all sources per step)",
         "value": seg_per_s,
@@ -231,7 +246,9 @@ def main():
                      "traffic_unit": "GB per trace (sum over the per-level k_sweep launches), "
                                      "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated",
                      "kernel": "k_sweep (one launch per HEALPix level)",
-                     "bytes_per_segment": BYTES_PER_SEGMENT,
+                     "bytes_per_segment": bps,
+                     "bytes_per_segment_with_accumulator_width":
+                         BYTES_PER_SEGMENT_FIXED_POINT if wl.deterministic else BYTES_PER_SEGMENT,
                      "sweep_ms_per_step": sweep_ms / args.steps,
                      "avg_launch_ms": avg_launch_ms},
         "cpu_baseline": cpu,

@@ -75,8 +75,8 @@ typedef struct {
     int enable_adjoint;      /* 1: also allocate the adjoint workspace */
     int64_t pool_rays;       /* ray-pool capacity (rays per source wave); 0 = size automatically */
     double pool_mem_fraction;/* automatic sizing: at most this fraction of free HBM (0 -> 0.5) */
-    int block_size;          /* threads per workgroup of the sweep kernels (64, 128, 192 or 256; 0 -> 256) */
-    int blocks_per_cu;       /* workgroups per CU launched for each sweep (0 -> 4) */
+    int block_size;          /* threads per workgroup of the sweep kernels (64, 128, 192 or 256; 0 -> 64) */
+    int blocks_per_cu;       /* workgroups per CU launched for each sweep (0 -> 16) */
 } art_options;
 
 /* Per-trace statistics (host copy).  Per-source arrays are indexed [src][level]

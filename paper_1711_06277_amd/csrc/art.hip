@@ -73,6 +73,8 @@ struct Pool {
     double* tau;      // [cap][2]: optical depth from the source at the ray's start
     uint32_t* child;  // pool index of the first of the four children (or kNoChild)
     double* G;        // [cap][2]: adjoint, loss contributed downstream of the start
+    double* tend;     // [cap][2]: optical depth where a splitting ray split; -1 if it did not
+    uint32_t* tsum;   // children per tile of kSplitTile parents, then their exclusive prefix
     uint64_t cap;
 };
 
@@ -117,6 +119,17 @@ struct AdjArgs {
     uint32_t n_src;
 };
 
+// Round y (a float with |y| < 2^62) to the nearest 64-bit integer: split |y|
+// at 2^32; the low part holds only bits of |y|'s 24-bit significand, so both
+// parts are exact and convert with the 32-bit FP32 conversions.
+__device__ __forceinline__ long long fixed_point(float y) {
+    const float a = fabsf(y);
+    const float hi = floorf(a * 0x1p-32f);
+    const float lo = a - hi * 0x1p32f;  // in [0, 2^32), exact
+    const long long m = (long long)(((unsigned long long)(unsigned)hi << 32) + (unsigned long long)(unsigned)rintf(lo));
+    return y < 0.0f ? -m : m;
+}
+
 __device__ __forceinline__ void fx_add(unsigned long long* p, double v, double scale) {
     const long long q = __double2ll_rn(v * scale);
     if (q != 0) atomicAdd(p, (unsigned long long)q);
@@ -158,7 +171,8 @@ __global__ void k_pack(uint64_t N, const float* nH, const float* xn, float2* q) 
 }
 
 // Reset the call counters; in deterministic mode also set the fixed-point
-// scale 2^60 / L_total (a cell can receive at most ~sqrt(3) L_total of J).
+// scale ~2^59..2^60 / L_total (a cell can receive at most ~sqrt(3) L_total of
+// J, so sums stay below 2^63).
 __global__ void k_begin_call(Counters* ct, const float* src_lum, int n_lum) {
     __shared__ double part[256];
     double s = 0.0;
@@ -175,8 +189,12 @@ __global__ void k_begin_call(Counters* ct, const float* src_lum, int n_lum) {
         ct->c.segments = 0ull;
         ct->c.rays_wave_max = 0ull;
         ct->c.status = 0u;
-        ct->c.scale = ldexp(1.0, 60) / L;
-        ct->c.inv_scale = L * ldexp(1.0, -60);
+        // a power of two, 2^59 / L <= scale < 2^60 / L, so that x * scale is
+        // exact in FP32 and its conversion to an integer is cheap
+        int k = 60 - ilogb(L) - 1;
+        k = k > 100 ? 100 : (k < -100 ? -100 : k);  // keep 2^k a normal FP32 number
+        ct->c.scale = ldexp(1.0, k);
+        ct->c.inv_scale = ldexp(1.0, -k);
     }
 }
 
@@ -265,9 +283,15 @@ __global__ void k_seed(Pool pool, Counters* ct, int level0, int src0, int n_wave
 //      list, which the whole wavefront flushes in converged code: lane l adds
 //      value (l mod LPE) of staged cell (l / LPE), so the NV values of a cell,
 //      contiguous in the AoS accumulator, share one memory transaction.
+// Both LDS arrays hold one row per value (slot h of value q at q * S + h): the
+// lanes of a wavefront address scattered slots, and with 8-byte values a
+// slot-major layout (stride 32 bytes) maps slots 0, 8, 16, ... onto the same
+// banks.  Every wavefront takes its part of the workgroup's dynamic LDS, so a
+// 64-thread workgroup needs a quarter of what a 256-thread one does.
 // Every step is executed in program order by the active lanes of one
 // wavefront and LDS executes a wavefront's instructions in order, so no barrier
-// is needed; keys, owners and the staging count are volatile (re-read from LDS).
+// is needed between lanes; compiler barriers keep the order of the LDS
+// operations of lanes in different branches.
 constexpr uint32_t kEmptyKey = 0xffffffffu;
 #define ART_LDS __attribute__((address_space(3)))
 
@@ -276,12 +300,26 @@ struct Deposit {
     using V = typename std::conditional<DET, unsigned long long, float>::type;
     static constexpr int S = 256;          // cache slots
     static constexpr int CAP = 128;        // staging capacity (>= 64 + flush threshold)
-    static constexpr int LPE = NV <= 4 ? 4 : 8;  // values per cell slot = AoS stride = lanes per staged cell
+    // Staging row stride: the flush reads rows f = 0..3 at one column each; a
+    // stride of 144 words puts those rows 16 (FP32) or 32 (64-bit) banks apart.
+    static constexpr int CAPP = CAP + 16;
+    static constexpr int LPE = NV <= 4 ? 4 : 8;  // AoS stride of the accumulator = lanes per staged cell
+    // LDS bytes per wavefront: values first (8-byte aligned), then the keys
+    static constexpr size_t kBytes = sizeof(V) * (size_t)NV * (S + CAPP) + sizeof(uint32_t) * (S + CAP);
     ART_LDS uint32_t* keys;                // [S]
-    ART_LDS V* vals;                       // [S][LPE]  (a slot's values contiguous)
+    ART_LDS V* vals;                       // [NV][S]: value q of slot h at q * S + h
     ART_LDS uint32_t* skey;                // [CAP]
-    ART_LDS V* sval;                       // [CAP][LPE]
+    ART_LDS V* sval;                       // [NV][CAPP]
     uint32_t n_staged;                     // wave-uniform
+
+    // Carve the wavefront's part out of the workgroup's dynamic LDS.
+    __device__ static inline Deposit at(unsigned char* base) {
+        ART_LDS unsigned char* b = (ART_LDS unsigned char*)base;
+        ART_LDS V* v = (ART_LDS V*)b;
+        ART_LDS V* sv = v + (size_t)NV * S;
+        ART_LDS uint32_t* k = (ART_LDS uint32_t*)(sv + (size_t)NV * CAPP);
+        return Deposit{k, v, k + S, sv, 0u};
+    }
 
     __device__ static inline uint32_t slot(const int (&ijk)[3]) {
         return (uint32_t)((ijk[0] & 7) | ((ijk[1] & 7) << 3) | ((ijk[2] & 3) << 6));
@@ -312,12 +350,12 @@ struct Deposit {
     // own deposit.  Returns true if (pk, pv) must be staged.
     __device__ inline bool deposit(uint32_t c, const int (&ijk)[3], const V (&v)[NV], uint32_t& pk, V (&pv)[NV]) {
         const uint32_t h = slot(ijk);
-        ART_LDS V* sv = vals + h * LPE;
+        ART_LDS V* sv = vals + h;
         const uint32_t key0 = keys[h];
         const bool hit = key0 == c;
         if (hit) {
 #pragma unroll
-            for (int q = 0; q < NV; ++q) lds_add(&sv[q], v[q]);
+            for (int q = 0; q < NV; ++q) lds_add(&sv[q * S], v[q]);
         }
         // Lanes that hit and lanes that evict run mutually exclusive branches,
         // so nothing orders them for the compiler: keep every add issued before
@@ -331,9 +369,9 @@ struct Deposit {
             pk = key0;
             pend = key0 != kEmptyKey;
 #pragma unroll
-            for (int q = 0; q < NV; ++q) pv[q] = sv[q];
+            for (int q = 0; q < NV; ++q) pv[q] = sv[q * S];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) sv[q] = v[q];
+            for (int q = 0; q < NV; ++q) sv[q * S] = v[q];
         }
         // lanes that lost the slot to a lane with the same cell add after the
         // winner has initialised it
@@ -341,7 +379,7 @@ struct Deposit {
         const bool follower = !hit && !won && prev == c;
         if (follower) {
 #pragma unroll
-            for (int q = 0; q < NV; ++q) lds_add(&sv[q], v[q]);
+            for (int q = 0; q < NV; ++q) lds_add(&sv[q * S], v[q]);
         }
         if (!hit && !won && !follower) {
             pk = c;
@@ -362,7 +400,7 @@ struct Deposit {
                                               (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
             skey[e] = pk;
 #pragma unroll
-            for (int q = 0; q < NV; ++q) sval[e * LPE + q] = pv[q];
+            for (int q = 0; q < NV; ++q) sval[q * CAPP + e] = pv[q];
         }
         n_staged += (uint32_t)__popcll(mk);
         lds_order();
@@ -380,7 +418,7 @@ struct Deposit {
             const uint32_t e = b0 + (uint32_t)lane / LPE;
             if (e < n && f < NV) {
                 V* p = acc + (uint64_t)skey[e] * LPE + f;
-                const V x = sval[e * LPE + f];
+                const V x = sval[f * CAPP + e];
                 if (DET) atomicAdd((unsigned long long*)p, (unsigned long long)x);
                 else unsafeAtomicAdd((float*)p, (float)x);
             }
@@ -396,7 +434,7 @@ struct Deposit {
             const uint32_t k = keys[s];
             V old[NV];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) old[q] = vals[s * LPE + q];
+            for (int q = 0; q < NV; ++q) old[q] = vals[q * S + s];
             stage(k != kEmptyKey, k, old);
             keys[s] = kEmptyKey;
             lds_order();
@@ -421,13 +459,8 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
     constexpr int NV = SweepVals<MODE>::NV;
     using Dep = Deposit<NV, DET>;
     using V = typename Dep::V;
-    constexpr int NW = 4;                       // wavefronts per workgroup (block size <= 256)
-    constexpr int SS = MODE ? Dep::S : 1;
-    constexpr int SC = MODE ? Dep::CAP : 1;
-    __shared__ uint32_t sh_keys[NW][SS];
-    __shared__ V sh_vals[NW][Dep::LPE * SS];
-    __shared__ uint32_t sh_skey[NW][SC];
-    __shared__ V sh_sval[NW][Dep::LPE * SC];
+    // Dynamic LDS: Dep::kBytes per wavefront of the workgroup (none in MODE 0)
+    extern __shared__ __align__(16) unsigned char sweep_lds[];
     const Geo& g = a.g;
     Counters* ct = a.ct;
     const int lane = lane_id();
@@ -446,11 +479,11 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
     V* acc = (V*)(DET ? (void*)a.det : (void*)a.acc);
 
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    Dep dep{(ART_LDS uint32_t*)sh_keys[w], (ART_LDS V*)sh_vals[w], (ART_LDS uint32_t*)sh_skey[w],
-            (ART_LDS V*)sh_sval[w], 0u};
+    Dep dep = Dep::at(sweep_lds + (MODE ? (size_t)w * Dep::kBytes : 0));
     if (MODE) dep.init(lane);
+    const float fscale = (float)scale;  // a power of two: x * fscale is exact
     auto quant = [&](float x) -> V {
-        if (DET) return (V)(unsigned long long)__double2ll_rn((double)x * scale);
+        if (DET) return (V)(unsigned long long)fixed_point(x * fscale);
         else return (V)x;
     };
 
@@ -535,7 +568,7 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
             }
             if (MODE) {
                 dep.stage(pend, pk, pv);
-                dep.flush(acc, lane, 64u);
+                dep.flush(acc, lane, (uint32_t)(Dep::CAP - kWave));
             }
         }
         const int end = m.end;
@@ -551,26 +584,15 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
             if (lane == 0) atomicOr(&ct->c.status, (uint32_t)kStStuck);
         }
 
-        // ---- children: four per splitting ray, appended to level l+1 ----
+        // ---- children: a splitting ray records the optical depth at the
+        //      split; the children are written in parent order afterwards ----
         const bool is_split = active && end == kSplit;
         const bool is_exit = active && end == kExit;
         const bool is_term = active && end == kTerm;
         const uint32_t nsplit = (uint32_t)__popcll(__ballot(is_split));
-        if (is_split) {
-            const uint64_t cs = off_next + (uint64_t)atomicAdd(&ct->w.tail[next], 4u);
-            if (cs + 4 <= a.pool.cap) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    a.pool.src[cs + k] = src;
-                    a.pool.pix[cs + k] = 4u * pix + (uint32_t)k;
-                    a.pool.tau[2 * (cs + k)] = tau[0];
-                    a.pool.tau[2 * (cs + k) + 1] = (NB > 1) ? tau[NB - 1] : 0.0;
-                    if (a.pool.child) a.pool.child[cs + k] = kNoChild;
-                }
-                if (a.pool.child) a.pool.child[slot] = (uint32_t)cs;
-            } else {
-                atomicOr(&ct->c.status, (uint32_t)kStOverflow);
-            }
+        if (active) {
+            a.pool.tend[2 * slot] = is_split ? tau[0] : -1.0;
+            a.pool.tend[2 * slot + 1] = (is_split && NB > 1) ? tau[NB - 1] : 0.0;
         }
 
         // ---- statistics: one atomic per counter per wavefront when the
@@ -620,6 +642,142 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
         }
     }
     if (MODE) dep.drain(acc, lane);
+}
+
+// --------------------------------------------------------------------------
+// Children of one level, in parent order
+// --------------------------------------------------------------------------
+
+// The seed kernel lays out level l0 by source, then by nested pixel.  Writing
+// the four children of the k-th splitting parent of a level to places 4k..4k+3
+// of the next level keeps every level in that order, so consecutive claims are
+// neighbouring directions of one source and the rays in flight at any moment
+// cover a small part of the grid (their gathers and deposits stay in cache).
+// Three passes per level: tiles of kSplitTile parents count their splitting
+// rays; one workgroup turns the counts into exclusive prefixes and sets the
+// next level's size; each tile then writes its children.
+constexpr int kSplitTile = 4096;
+constexpr int kSplitThreads = 256;
+
+// The level's rays [off, off + n); none after a pool overflow, when the tree is
+// incomplete and the error is reported on synchronisation.
+__device__ inline void level_range(const Pool& pool, const Counters* ct, int level, uint64_t& off, uint32_t& n) {
+    off = ct->w.off[level];
+    const uint32_t t = ct->w.tail[level];
+    n = (uint32_t)std::min<uint64_t>(t, pool.cap > off ? pool.cap - off : 0);
+    if (ct->c.status & kStOverflow) n = 0;
+}
+
+__global__ void __launch_bounds__(kSplitThreads) k_split_count(Pool pool, const Counters* ct, int level) {
+    __shared__ uint32_t part[kSplitThreads / kWave];
+    uint64_t off;
+    uint32_t n;
+    level_range(pool, ct, level, off, n);
+    const uint32_t n_tiles = (n + kSplitTile - 1) / kSplitTile;
+    const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
+    for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        uint32_t cnt = 0;
+        for (uint32_t j = threadIdx.x; j < kSplitTile; j += kSplitThreads) {
+            const uint32_t i = t * kSplitTile + j;
+            if (i < n && pool.tend[2 * (off + i)] >= 0.0) ++cnt;
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
+        if (lane == 0) part[w] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t s = 0;
+            for (int k = 0; k < kSplitThreads / kWave; ++k) s += part[k];
+            pool.tsum[t] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup: exclusive prefix of the tile counts (in place); sets the
+// next level's ray count, or the overflow status if the pool cannot hold it.
+__global__ void __launch_bounds__(1024) k_split_scan(Pool pool, Counters* ct, int level) {
+    __shared__ uint32_t part[1024 / kWave];
+    __shared__ uint32_t carry_sh;
+    uint64_t off;
+    uint32_t n;
+    level_range(pool, ct, level, off, n);
+    const uint32_t n_tiles = (n + kSplitTile - 1) / kSplitTile;
+    const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
+    if (threadIdx.x == 0) carry_sh = 0u;
+    __syncthreads();
+    for (uint32_t b = 0; b < n_tiles; b += blockDim.x) {
+        const uint32_t t = b + threadIdx.x;
+        const uint32_t v = t < n_tiles ? pool.tsum[t] : 0u;
+        uint32_t x = v;  // inclusive scan within the wavefront
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, kWave);
+            if (lane >= o) x += y;
+        }
+        if (lane == kWave - 1) part[w] = x;
+        __syncthreads();
+        uint32_t before = carry_sh;
+        for (int k = 0; k < w; ++k) before += part[k];
+        if (t < n_tiles) pool.tsum[t] = before + x - v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t s = 0;
+            for (int k = 0; k < (int)(blockDim.x / kWave); ++k) s += part[k];
+            carry_sh += s;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && level + 1 <= ART_MAX_LEVELS) {
+        const uint64_t kids = 4ull * carry_sh;
+        const uint64_t off_next = off + n;
+        if (off_next + kids > pool.cap) atomicOr(&ct->c.status, (uint32_t)kStOverflow);
+        ct->w.tail[level + 1] = (uint32_t)std::min<uint64_t>(kids, 0xffffffffull);
+    }
+}
+
+__global__ void __launch_bounds__(kSplitThreads) k_split_scatter(Pool pool, const Counters* ct, int level) {
+    __shared__ uint32_t part[kSplitThreads / kWave];
+    uint64_t off;
+    uint32_t n;
+    level_range(pool, ct, level, off, n);
+    const uint64_t off_next = off + n;
+    const uint32_t n_tiles = (n + kSplitTile - 1) / kSplitTile;
+    const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
+    for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        uint32_t carry = pool.tsum[t];
+        for (uint32_t j0 = 0; j0 < kSplitTile; j0 += kSplitThreads) {
+            const uint32_t i = t * kSplitTile + j0 + threadIdx.x;
+            const uint64_t s = off + i;
+            const bool sp = i < n && pool.tend[2 * s] >= 0.0;
+            const unsigned long long m = __ballot(sp);
+            if (lane == 0) part[w] = (uint32_t)__popcll(m);
+            __syncthreads();
+            uint32_t before = carry, all = 0;
+            for (int k = 0; k < kSplitThreads / kWave; ++k) {
+                if (k < w) before += part[k];
+                all += part[k];
+            }
+            if (sp) {
+                const uint32_t r = before + (uint32_t)__builtin_amdgcn_mbcnt_hi(
+                                                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                const uint64_t cs = off_next + 4ull * r;
+                if (cs + 4 <= pool.cap) {
+                    const uint32_t src = pool.src[s], pix = pool.pix[s];
+                    const double t0 = pool.tend[2 * s], t1 = pool.tend[2 * s + 1];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        pool.src[cs + k] = src;
+                        pool.pix[cs + k] = 4u * pix + (uint32_t)k;
+                        pool.tau[2 * (cs + k)] = t0;
+                        pool.tau[2 * (cs + k) + 1] = t1;
+                        if (pool.child) pool.child[cs + k] = kNoChild;
+                    }
+                    if (pool.child) pool.child[s] = (uint32_t)cs;
+                }
+            }
+            carry += all;
+            __syncthreads();
+        }
+    }
 }
 
 // After the deepest level of a wave: record the number of rays the wave held.
@@ -937,6 +1095,8 @@ void free_all(art_ctx* c) {
     (void)hipFree(c->pool.tau);
     (void)hipFree(c->pool.child);
     (void)hipFree(c->pool.G);
+    (void)hipFree(c->pool.tend);
+    (void)hipFree(c->pool.tsum);
     (void)hipFree(c->ct);
     (void)hipFree(c->st.created);
     (void)hipFree(c->st.split);
@@ -985,13 +1145,20 @@ SweepArgs sweep_args(art_ctx* c, const float* nH, const float* xn, const double*
 }
 
 // mode 0: J0 only (adjoint tape pass); 1: J0 + force; 2: J0 + force + J1
+template <bool DET, int MODE>
+size_t sweep_lds_bytes(unsigned block) {
+    return MODE ? (size_t)(block / kWave) * Deposit<SweepVals<MODE>::NV, DET>::kBytes : 0;
+}
+
 int launch_sweep(art_ctx* c, const SweepArgs& a, int level, int mode) {
     const dim3 grid((unsigned)(c->cu_count * c->o.blocks_per_cu)), block((unsigned)c->o.block_size);
     const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
     const int nb = c->p.n_bins;
     const bool tm = c->timing && c->ev_used + 2 <= (int)c->ev.size();
     if (tm) HIP_TRY(hipEventRecord(c->ev[c->ev_used], c->stream));
-#define SWEEP(NB, DET, MODE) hipLaunchKernelGGL((k_sweep<NB, DET, MODE>), grid, block, 0, c->stream, a, level)
+#define SWEEP(NB, DET, MODE)                                                                      \
+    hipLaunchKernelGGL((k_sweep<NB, DET, MODE>), grid, block, (sweep_lds_bytes<DET, MODE>(block.x)), c->stream, a, \
+                       level)
     if (nb == 1) {
         if (det) { if (mode) SWEEP(1, true, 1); else SWEEP(1, true, 0); }
         else { if (mode) SWEEP(1, false, 1); else SWEEP(1, false, 0); }
@@ -1032,10 +1199,21 @@ int seed_wave(art_ctx* c, int s0, int n_wave) {
 }
 
 // Sweep every level of the current wave, l0 first.
+// Children of level l, in parent order (see k_split_count).
+int split_level(art_ctx* c, int l) {
+    const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(4096, (c->pool.cap + kSplitTile - 1) / kSplitTile));
+    hipLaunchKernelGGL(k_split_count, dim3(blocks), dim3(kSplitThreads), 0, c->stream, c->pool, c->ct, l);
+    hipLaunchKernelGGL(k_split_scan, dim3(1), dim3(1024), 0, c->stream, c->pool, c->ct, l);
+    hipLaunchKernelGGL(k_split_scatter, dim3(blocks), dim3(kSplitThreads), 0, c->stream, c->pool, c->ct, l);
+    HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+
 int sweep_wave(art_ctx* c, const SweepArgs& a, int mode) {
     for (int l = c->p.level0; l <= c->p.level_max; ++l) {
         int rc = launch_sweep(c, a, l, mode);
         if (rc) return rc;
+        if (l < c->p.level_max && (rc = split_level(c, l))) return rc;
     }
     hipLaunchKernelGGL(k_end_wave, dim3(1), dim3(64), 0, c->stream, c->ct, c->p.level0, c->p.level_max);
     HIP_TRY(hipGetLastError());
@@ -1081,8 +1259,8 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
     memset(&o, 0, sizeof o);
     if (opts) o = *opts;
     if (o.max_sources <= 0) return ART_ERR_INVALID_ARG;
-    if (o.block_size == 0) o.block_size = 256;
-    if (o.blocks_per_cu == 0) o.blocks_per_cu = 4;
+    if (o.block_size == 0) o.block_size = 64;
+    if (o.blocks_per_cu == 0) o.blocks_per_cu = 16;
     if (o.block_size < 64 || o.block_size > 256 || (o.block_size % 64) || o.blocks_per_cu < 1 ||
         o.blocks_per_cu > 64)
         return ART_ERR_INVALID_ARG;
@@ -1117,7 +1295,7 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
 
     // ray pool
     c->per_src_bound = rays_bound_per_source(nx, ny, nz, *params);
-    const uint64_t bytes_per_ray = 4 + 4 + 16 + (o.enable_adjoint ? 4 + 16 : 0);
+    const uint64_t bytes_per_ray = 4 + 4 + 16 + 16 + (o.enable_adjoint ? 4 + 16 : 0);
     uint64_t cap = (uint64_t)o.pool_rays;
     if (cap == 0) {
         size_t free_b = 0, total_b = 0;
@@ -1143,6 +1321,7 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
     const bool det = params->deposit_mode == ART_DEPOSIT_DETERMINISTIC;
     const uint64_t ms = (uint64_t)o.max_sources;
     bool ok = dmalloc(&c->pool.src, cap) && dmalloc(&c->pool.pix, cap) && dmalloc(&c->pool.tau, 2 * cap) &&
+              dmalloc(&c->pool.tend, 2 * cap) && dmalloc(&c->pool.tsum, (cap + kSplitTile - 1) / kSplitTile + 1) &&
               dmalloc(&c->ct, 1) && dmalloc(&c->st.created, ms * ART_MAX_LEVELS) &&
               dmalloc(&c->st.split, ms * ART_MAX_LEVELS) && dmalloc(&c->st.exited, ms * ART_MAX_LEVELS) &&
               dmalloc(&c->st.term, ms * ART_MAX_LEVELS) && dmalloc(&c->st.escaped, ms * 2) &&
@@ -1382,7 +1561,7 @@ int art_get_timing(art_ctx* c, float* sweep_ms_total, int* sweep_launches, float
 int art_autotune(art_ctx* c, const float* n_H, const float* x_n, const double* src_pos, const float* src_lum,
                  int n_src, float* rate, float* force, int* best_block, int* best_bpc, float* best_ms) {
     if (!c) return ART_ERR_INVALID_ARG;
-    static const int cand[][2] = {{64, 8}, {64, 16}, {128, 4}, {128, 8}, {256, 2}, {256, 4}, {256, 8}};
+    static const int cand[][2] = {{64, 8}, {64, 12}, {64, 16}, {128, 4}, {128, 6}, {256, 2}, {256, 4}};
     const art_options keep = c->o;
     const bool keep_timing = c->timing;
     c->timing = true;
