@@ -28,6 +28,9 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 # method's 40 B in both modes.
 BYTES_PER_SEGMENT = 40
 BYTES_PER_SEGMENT_FIXED_POINT = 72
+# the adjoint walks every segment twice: both passes gather (n_H, x_n, w, v)
+# (24 B), the second adds dL/dn_H and dL/dx_n to two FP64 cells (2 x 16 B RMW)
+ADJOINT_BYTES_PER_SEGMENT = 80
 
 
 def log(*a):
@@ -71,6 +74,7 @@ def main():
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--no-plain", action="store_true", help="skip the one-source-per-call timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint sweep timing")
     ap.add_argument("--atomic", action="store_true",
                     help="FP32 atomic deposits instead of the (faster) 64-bit fixed-point ones")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -194,6 +198,55 @@ def main():
         log(f"[bench] plain: {1e3 * t_plain:.2f} ms for {wl.n_src} sources, speedup "
             f"{plain['speedup_batched_over_plain']:.2f}x, max rel diff {rel:.2e}")
 
+    # ---- adjoint: the forward trace records the tree, then the adjoint sweep
+    #      computes dL/dn_H and dL/dx_n for L = <w, rate> + <v, force> ----
+    adjoint = None
+    if not args.no_adjoint:
+        tr.close()
+        tr = None
+        ta = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
+                       level0=wl.level0, level_max=wl.level_max, phi_c=wl.phi_c,
+                       tau_term=wl.tau_term, deterministic=wl.deterministic,
+                       max_sources=wl.n_src, enable_adjoint=True, block_size=args.block_size,
+                       blocks_per_cu=args.blocks_per_cu, device=dev)
+        w_np, v_np = I.random_adjoint_weights(N, seed=7000 + args.workload)
+        w = torch.from_numpy(w_np).to(dev)
+        v = torch.from_numpy(v_np).to(dev)
+        g_nH = torch.empty(N, dtype=torch.float32, device=dev)
+        g_xn = torch.empty(N, dtype=torch.float32, device=dev)
+        ta.trace(nH, xn, pos, lum, out=out, check=False)
+        ta.adjoint(nH, xn, pos, lum, w, v, out=(g_nH, g_xn), check=False)
+        rc = ta.sync()
+        t_fwd = t_adj = 0.0
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            ta0 = time.perf_counter()
+            ta.trace(nH, xn, pos, lum, out=out, check=False)
+            torch.cuda.synchronize()
+            ta1 = time.perf_counter()
+            ta.adjoint(nH, xn, pos, lum, w, v, out=(g_nH, g_xn), check=False)
+            torch.cuda.synchronize()
+            ta2 = time.perf_counter()
+            t_fwd += ta1 - ta0
+            t_adj += ta2 - ta1
+        rc = rc or ta.sync()
+        finite = bool(torch.isfinite(g_nH).all().item() and torch.isfinite(g_xn).all().item())
+        ta.close()
+        adj_s = t_adj / args.steps
+        adj_gbs = segments * ADJOINT_BYTES_PER_SEGMENT / adj_s / 1e9
+        adjoint = {"ms_per_adjoint": 1e3 * adj_s,
+                   "ms_per_forward_with_tree": 1e3 * t_fwd / args.steps,
+                   "segments_per_s": segments / adj_s,
+                   "status": rc, "gradients_finite": finite,
+                   "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": adj_gbs / HBM_PEAK_GBS,
+                                "kernel": "k_adjoint (one launch per level, deepest first; "
+                                          "both passes over every segment)",
+                                "bytes_per_segment": ADJOINT_BYTES_PER_SEGMENT}}
+        log(f"[bench] adjoint: {1e3 * adj_s:.2f} ms per adjoint sweep "
+            f"({segments / adj_s:.3e} segments/s), forward with tree "
+            f"{1e3 * t_fwd / args.steps:.2f} ms, status {rc}")
+
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device=dev)
@@ -217,7 +270,8 @@ def main():
                "ms_per_trace_per_source": 1e3 * dt}
         log(f"[bench] oracle: {seg_cpu / dt:.3e} segments/s on one core ({dt:.1f} s)")
 
-    tr.close()
+    if tr is not None:
+        tr.close()
     traffic = measured_traffic(args.workload, wl.deterministic)
     result = {
         "metric": "ray-cell segments/s (batched, one full trace of all sources per step)",
@@ -240,6 +294,7 @@ def main():
                    "deposit": "deterministic" if wl.deterministic else "atomic",
                    "segments_per_trace": segments, "waves": st.n_waves},
         "plain": plain,
+        "adjoint": adjoint,
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic / 1e9,
