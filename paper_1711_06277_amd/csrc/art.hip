@@ -105,16 +105,14 @@ struct SweepArgs {
 
 struct AdjArgs {
     Geo g;
-    const float* nH;
-    const float* xn;
+    const float2* q;   // (n_H, x_n) per cell
+    const float4* wv;  // (w, v_x, v_y, v_z) per cell: the weights of rate and force in L
     const double* src_pos;
     const float* src_lum;
-    const float* w;   // [N]
-    const float* v;   // [3][N]
     Pool pool;
     Counters* ct;
-    double* gk;                // [2][N] dL/dn_H, dL/dx_n (FP64 atomics)
-    unsigned long long* gdet;  // [2][N] the same in fixed point
+    double* gk;                // [N][2] (dL/dn_H, dL/dx_n) per cell, FP64
+    unsigned long long* gdet;  // [N][2] the same in fixed point
     uint32_t N;
     uint32_t n_src;
 };
@@ -130,10 +128,6 @@ __device__ __forceinline__ long long fixed_point(float y) {
     return y < 0.0f ? -m : m;
 }
 
-__device__ __forceinline__ void fx_add(unsigned long long* p, double v, double scale) {
-    const long long q = __double2ll_rn(v * scale);
-    if (q != 0) atomicAdd(p, (unsigned long long)q);
-}
 
 // --------------------------------------------------------------------------
 // Small kernels
@@ -168,6 +162,13 @@ __global__ void k_pack(uint64_t N, const float* nH, const float* xn, float2* q) 
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N;
          i += (uint64_t)gridDim.x * blockDim.x)
         q[i] = make_float2(nH[i], xn[i]);
+}
+
+// The adjoint's per-cell weights in one 16-byte gather: (w, v_x, v_y, v_z).
+__global__ void k_pack_wv(uint64_t N, const float* w, const float* v, float4* wv) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        wv[i] = make_float4(w[i], v[i], v[N + i], v[2 * N + i]);
 }
 
 // Reset the call counters; in deterministic mode also set the fixed-point
@@ -295,15 +296,15 @@ __global__ void k_seed(Pool pool, Counters* ct, int level0, int src0, int n_wave
 constexpr uint32_t kEmptyKey = 0xffffffffu;
 #define ART_LDS __attribute__((address_space(3)))
 
-template <int NV, bool DET>
+template <int NV, class V_>
 struct Deposit {
-    using V = typename std::conditional<DET, unsigned long long, float>::type;
+    using V = V_;  // float, double, or unsigned 64-bit fixed point (two's complement sums)
     static constexpr int S = 256;          // cache slots
     static constexpr int CAP = 128;        // staging capacity (>= 64 + flush threshold)
     // Staging row stride: the flush reads rows f = 0..3 at one column each; a
     // stride of 144 words puts those rows 16 (FP32) or 32 (64-bit) banks apart.
     static constexpr int CAPP = CAP + 16;
-    static constexpr int LPE = NV <= 4 ? 4 : 8;  // AoS stride of the accumulator = lanes per staged cell
+    static constexpr int LPE = NV <= 2 ? 2 : (NV <= 4 ? 4 : 8);  // AoS stride of the accumulator = lanes per staged cell
     // LDS bytes per wavefront: values first (8-byte aligned), then the keys
     static constexpr size_t kBytes = sizeof(V) * (size_t)NV * (S + CAPP) + sizeof(uint32_t) * (S + CAP);
     ART_LDS uint32_t* keys;                // [S]
@@ -327,9 +328,15 @@ struct Deposit {
     __device__ static inline void lds_add(ART_LDS float* p, float x) {
         __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
+    __device__ static inline void lds_add(ART_LDS double* p, double x) {
+        __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
     __device__ static inline void lds_add(ART_LDS unsigned long long* p, unsigned long long x) {
         __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
+    __device__ static inline void global_add(float* p, float x) { unsafeAtomicAdd(p, x); }
+    __device__ static inline void global_add(double* p, double x) { unsafeAtomicAdd(p, x); }
+    __device__ static inline void global_add(unsigned long long* p, unsigned long long x) { atomicAdd(p, x); }
 
     // Compiler-only barrier: LDS operations of different lanes in different
     // branches are not reordered across it.
@@ -417,10 +424,7 @@ struct Deposit {
         for (uint32_t b0 = 0; b0 < n; b0 += per) {
             const uint32_t e = b0 + (uint32_t)lane / LPE;
             if (e < n && f < NV) {
-                V* p = acc + (uint64_t)skey[e] * LPE + f;
-                const V x = sval[f * CAPP + e];
-                if (DET) atomicAdd((unsigned long long*)p, (unsigned long long)x);
-                else unsafeAtomicAdd((float*)p, (float)x);
+                global_add(acc + (uint64_t)skey[e] * LPE + f, sval[f * CAPP + e]);
             }
         }
         n_staged = 0u;
@@ -457,7 +461,7 @@ struct SweepVals {
 template <int NB, bool DET, int MODE>
 __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
     constexpr int NV = SweepVals<MODE>::NV;
-    using Dep = Deposit<NV, DET>;
+    using Dep = Deposit<NV, typename std::conditional<DET, unsigned long long, float>::type>;
     using V = typename Dep::V;
     // Dynamic LDS: Dep::kBytes per wavefront of the workgroup (none in MODE 0)
     extern __shared__ __align__(16) unsigned char sweep_lds[];
@@ -830,123 +834,185 @@ __global__ void k_finalize(uint64_t N, const float* nH, const float* xn, double 
 // with a = w s_H x_n n_H (the rate weight) and beta = v . n (the force weight):
 // every downstream contribution is proportional to e^{-tau}, so its derivative
 // with respect to this segment's opacity is -dr times its value.
-template <int NB, bool DET>
-__device__ inline void adjoint_ray(const AdjArgs& a, Counters* ct, int level, uint64_t slot, double gscale) {
-    const Geo& g = a.g;
-    const uint32_t N = a.N;
-    const uint32_t src = a.pool.src[slot];
-    const uint32_t pix = a.pool.pix[slot];
-    if (src >= a.n_src) return;
-    double tau0[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) tau0[b] = a.pool.tau[2 * slot + b];
-    Ray r;
-    ray_setup(g, a.src_pos, src, level, pix, r);
-    double Gend[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) Gend[b] = 0.0;
-    const uint32_t ch = a.pool.child[slot];
-    if (ch != kNoChild) {
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int b = 0; b < NB; ++b) Gend[b] += a.pool.G[2 * ((uint64_t)ch + k) + b];
-    }
-    double T[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) T[b] = 0.0;
-    if (source_inside(g, r.xs) && !r.starts_outside) {
-        // The gradient of a cell is a sum of terms of both signs (the explicit
-        // absorption terms against -dr G of everything downstream), so the
-        // per-segment arithmetic and the accumulation are FP64 here.
-        double lnom[NB];
-        const double inv_nray = 1.0 / (12.0 * ldexp(1.0, 2 * level));
-#pragma unroll
-        for (int b = 0; b < NB; ++b) lnom[b] = (double)a.src_lum[(uint64_t)src * NB + b] * inv_nray;
-        const double sH = g.s_H;
-        bool stuck = false;
-        // pass 1: the ray's own loss contributions T_b
-        double tau[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) tau[b] = tau0[b];
-        march<NB>(g, a.nH, a.xn, r, tau, &stuck,
-            [&](uint32_t c, const int (&ijk)[3], double dr, const double (&dtau)[NB], const double (&tin)[NB]) {
-                const double wa = (double)a.w[c] * sH * (double)a.xn[c] * (double)a.nH[c];
-                const double beta = (double)a.v[c] * r.n[0] + (double)a.v[(uint64_t)N + c] * r.n[1] +
-                                    (double)a.v[2ull * N + c] * r.n[2];
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const double x = dtau[b];
-                    const double Lin = lnom[b] * exp(-tin[b]);
-                    const double om = -expm1(-x);
-                    double own = beta * Lin * om;
-                    if (b == 0) own += wa * Lin * dr * absorb_phi(x, om);
-                    T[b] += own;
-                }
-            });
-        // pass 2: dL/dkappa_b of every crossed cell
-        double P[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            P[b] = 0.0;
-            tau[b] = tau0[b];
-        }
-        march<NB>(g, a.nH, a.xn, r, tau, &stuck,
-            [&](uint32_t c, const int (&ijk)[3], double dr, const double (&dtau)[NB], const double (&tin)[NB]) {
-                const double wa = (double)a.w[c] * sH * (double)a.xn[c] * (double)a.nH[c];
-                const double beta = (double)a.v[c] * r.n[0] + (double)a.v[(uint64_t)N + c] * r.n[1] +
-                                    (double)a.v[2ull * N + c] * r.n[2];
-                double dkap[NB];
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const double x = dtau[b];
-                    const double Lin = lnom[b] * exp(-tin[b]);
-                    const double om = -expm1(-x);
-                    const double e = 1.0 - om;
-                    double own = beta * Lin * om;
-                    double dk = beta * Lin * dr * e;
-                    if (b == 0) {
-                        own += wa * Lin * dr * absorb_phi(x, om);
-                        dk += wa * Lin * dr * dr * absorb_dphi(x, e, om);
-                    }
-                    P[b] += own;
-                    const double after = (T[b] - P[b]) + Gend[b];
-                    dkap[b] = dk - dr * after;
-                }
-                // chain rule through kappa_0 = n_H (x_n s_H + s_d), kappa_1 = n_H s_d,
-                // plus the explicit n_H x_n factor of rate = s_H x_n n_H J_0
-                const double xv = (double)a.xn[c], nv = (double)a.nH[c];
-                const double j0 = lnom[0] * exp(-tin[0]) * dr * absorb_phi(dtau[0], -expm1(-dtau[0]));
-                const double wj = (double)a.w[c] * sH * j0;
-                double gn = dkap[0] * (xv * sH + g.s_d) + wj * xv;
-                if (NB > 1) gn += dkap[NB - 1] * g.s_d;
-                const double gx = dkap[0] * nv * sH + wj * nv;
-                if (DET) {
-                    fx_add(&a.gdet[c], gn, gscale);
-                    fx_add(&a.gdet[(uint64_t)N + c], gx, gscale);
-                } else {
-                    unsafeAtomicAdd(&a.gk[c], gn);
-                    unsafeAtomicAdd(&a.gk[(uint64_t)N + c], gx);
-                }
-            });
-        if (stuck) atomicOr(&ct->c.status, (uint32_t)kStStuck);
-    }
-#pragma unroll
-    for (int b = 0; b < NB; ++b) a.pool.G[2 * slot + b] = T[b] + Gend[b];
-}
-
+//
+// The walk is the forward sweep's (march_step over the same packed fields), so
+// the segments and the tree are the forward's.  The transmission e^{-tau_b}
+// is carried along the ray as a product of the segments' e^{-dtau}, identical
+// in both passes, so P_b (pass 2's running sum of the own terms) reaches T_b
+// exactly at the ray's end.  The gradient of a cell is a sum of terms of both
+// signs (the explicit absorption terms against -dr G of everything
+// downstream), so the per-segment arithmetic is FP64 and the two values per
+// cell go through the same LDS cache as the forward deposits, as FP64 or as
+// 64-bit fixed point.
 template <int NB, bool DET>
 __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
+    using V = typename std::conditional<DET, unsigned long long, double>::type;
+    using Dep = Deposit<2, V>;
+    extern __shared__ __align__(16) unsigned char adj_lds[];
+    const Geo& g = a.g;
     Counters* ct = a.ct;
     if (ct->c.status & kStOverflow) return;
+    const int lane = lane_id();
     const uint64_t off = ct->w.off[level];
     const uint32_t n_level =
         (uint32_t)std::min<uint64_t>(ct->w.tail[level], a.pool.cap > off ? a.pool.cap - off : 0);
     const double gscale = DET ? ct->c.gscale : 0.0;
+    const double inv_nray = 1.0 / (12.0 * ldexp(1.0, 2 * level));
+    const double sH = g.s_H, sd = g.s_d;
+    V* acc = (V*)(DET ? (void*)a.gdet : (void*)a.gk);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    Dep dep = Dep::at(adj_lds + (size_t)w * Dep::kBytes);
+    dep.init(lane);
+    auto quant = [&](double x) -> V {
+        if (DET) return (V)(unsigned long long)__double2ll_rn(x * gscale);
+        else return (V)x;
+    };
+
     for (;;) {
         const uint32_t li = atomicAdd(&ct->w.adj_head[level], 1u);
-        if (__ballot(li < n_level) == 0ull) break;
-        if (li < n_level) adjoint_ray<NB, DET>(a, ct, level, off + li, gscale);
+        const bool active = li < n_level;
+        if (__ballot(active) == 0ull) break;
+        const uint64_t slot = off + (active ? li : 0u);
+
+        uint32_t src = 0, pix = 0;
+        double tau0[NB], E0[NB], lnom[NB], Gend[NB], T[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            tau0[b] = 0.0;
+            E0[b] = 1.0;
+            lnom[b] = 0.0;
+            Gend[b] = 0.0;
+            T[b] = 0.0;
+        }
+        bool run = false, stuck = false;
+        Ray r;
+        if (active) {
+            src = a.pool.src[slot];
+            pix = a.pool.pix[slot];
+            const bool ok = src < a.n_src;  // always true for a written slot
+            if (!ok) src = 0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                tau0[b] = a.pool.tau[2 * slot + b];
+                E0[b] = exp(-tau0[b]);
+                lnom[b] = (double)a.src_lum[(uint64_t)src * NB + b] * inv_nray;
+            }
+            const uint32_t ch = a.pool.child[slot];
+            if (ch != kNoChild) {
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) Gend[b] += a.pool.G[2 * ((uint64_t)ch + k) + b];
+            }
+            ray_setup(g, a.src_pos, src, level, pix, r);
+            run = ok && source_inside(g, r.xs) && !r.starts_outside;
+        }
+        const double nx = r.n[0], ny = r.n[1], nz = r.n[2];
+
+        // ---- pass 1: T_b, the ray's own loss contributions ----
+        MarchState m;
+        m.alive = false;
+        m.end = kExit;
+        double tau[NB], E[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            tau[b] = tau0[b];
+            E[b] = E0[b];
+        }
+        if (run) march_begin(g, a.q, r, m);
+        while (__ballot(m.alive)) {
+            uint32_t c;
+            int ijk[3];
+            double dr, dtau[NB], tin[NB];
+            const float2 qc = m.q;
+            if (march_step<NB>(g, a.q, r, m, tau, &stuck, c, ijk, dr, dtau, tin)) {
+                const float4 wv = a.wv[c];
+                const double wa = (double)wv.x * sH * (double)qc.y * (double)qc.x;
+                const double beta = (double)wv.y * nx + (double)wv.z * ny + (double)wv.w * nz;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const double x = dtau[b];
+                    const double Lin = lnom[b] * E[b];
+                    const double om = -expm1(-x);
+                    double own = beta * Lin * om;
+                    if (b == 0) own += wa * Lin * dr * absorb_phi(x, om);
+                    T[b] += own;
+                    E[b] *= 1.0 - om;
+                }
+            }
+        }
+
+        // ---- pass 2: dL/dkappa_b of every crossed cell ----
+        m.alive = false;
+        double P[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            tau[b] = tau0[b];
+            E[b] = E0[b];
+            P[b] = 0.0;
+        }
+        if (run) march_begin(g, a.q, r, m);
+        while (__ballot(m.alive)) {
+            bool pend = false;
+            uint32_t pk = 0;
+            V pv[2];
+            {
+                uint32_t c;
+                int ijk[3];
+                double dr, dtau[NB], tin[NB];
+                const float2 qc = m.q;
+                if (march_step<NB>(g, a.q, r, m, tau, &stuck, c, ijk, dr, dtau, tin)) {
+                    const float4 wv = a.wv[c];
+                    const double xv = (double)qc.y, nv = (double)qc.x;
+                    const double wa = (double)wv.x * sH * xv * nv;
+                    const double beta = (double)wv.y * nx + (double)wv.z * ny + (double)wv.w * nz;
+                    double dkap[NB], j0 = 0.0;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const double x = dtau[b];
+                        const double Lin = lnom[b] * E[b];
+                        const double om = -expm1(-x);
+                        const double e = 1.0 - om;
+                        double own = beta * Lin * om;
+                        double dk = beta * Lin * dr * e;
+                        if (b == 0) {
+                            const double ph = absorb_phi(x, om);
+                            j0 = Lin * dr * ph;
+                            own += wa * j0;
+                            dk += wa * Lin * dr * dr * absorb_dphi(x, e, om);
+                        }
+                        P[b] += own;
+                        const double after = (T[b] - P[b]) + Gend[b];
+                        dkap[b] = dk - dr * after;
+                        E[b] *= e;
+                    }
+                    // chain rule through kappa_0 = n_H (x_n s_H + s_d), kappa_1 = n_H s_d,
+                    // plus the explicit n_H x_n factor of rate = s_H x_n n_H J_0
+                    const double wj = (double)wv.x * sH * j0;
+                    double gn = dkap[0] * (xv * sH + sd) + wj * xv;
+                    if (NB > 1) gn += dkap[NB - 1] * sd;
+                    const double gx = dkap[0] * nv * sH + wj * nv;
+                    V v[2] = {quant(gn), quant(gx)};
+                    pend = dep.deposit(c, ijk, v, pk, pv);
+                }
+            }
+            dep.stage(pend, pk, pv);
+            dep.flush(acc, lane, (uint32_t)(Dep::CAP - kWave));
+        }
+        if (__ballot(stuck)) {
+            if (lane == 0) atomicOr(&ct->c.status, (uint32_t)kStStuck);
+        }
+        if (active) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) a.pool.G[2 * slot + b] = T[b] + Gend[b];
+        }
     }
+    dep.drain(acc, lane);
+}
+
+template <int NB, bool DET>
+size_t adjoint_lds_bytes(unsigned block) {
+    using V = typename std::conditional<DET, unsigned long long, double>::type;
+    return (size_t)(block / kWave) * Deposit<2, V>::kBytes;
 }
 
 // Convert the accumulated dL/dn_H and dL/dx_n to the FP32 outputs.
@@ -957,11 +1023,11 @@ __global__ void k_adj_finalize(uint64_t N, const double* gk, const unsigned long
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N;
          c += (uint64_t)gridDim.x * blockDim.x) {
         if (DET) {
-            g_nH[c] = (float)((double)(long long)gdet[c] * ginv);
-            g_xn[c] = (float)((double)(long long)gdet[N + c] * ginv);
+            g_nH[c] = (float)((double)(long long)gdet[2 * c] * ginv);
+            g_xn[c] = (float)((double)(long long)gdet[2 * c + 1] * ginv);
         } else {
-            g_nH[c] = (float)gk[c];
-            g_xn[c] = (float)gk[N + c];
+            g_nH[c] = (float)gk[2 * c];
+            g_xn[c] = (float)gk[2 * c + 1];
         }
     }
 }
@@ -992,6 +1058,7 @@ struct art_ctx {
     unsigned long long* gdet;
     float* fscratch;
     float2* q;                // [N] packed (n_H, x_n)
+    float4* wv;               // [N] packed adjoint weights (w, v_x, v_y, v_z)
     // tape of the last forward (valid only for a single-wave trace)
     const void* tape_key[4];
     int tape_nsrc;
@@ -1111,6 +1178,7 @@ void free_all(art_ctx* c) {
     (void)hipFree(c->gdet);
     (void)hipFree(c->fscratch);
     (void)hipFree(c->q);
+    (void)hipFree(c->wv);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->ev_call0) (void)hipEventDestroy(c->ev_call0);
     if (c->ev_call1) (void)hipEventDestroy(c->ev_call1);
@@ -1147,7 +1215,9 @@ SweepArgs sweep_args(art_ctx* c, const float* nH, const float* xn, const double*
 // mode 0: J0 only (adjoint tape pass); 1: J0 + force; 2: J0 + force + J1
 template <bool DET, int MODE>
 size_t sweep_lds_bytes(unsigned block) {
-    return MODE ? (size_t)(block / kWave) * Deposit<SweepVals<MODE>::NV, DET>::kBytes : 0;
+    return MODE ? (size_t)(block / kWave) *
+                      Deposit<SweepVals<MODE>::NV, typename std::conditional<DET, unsigned long long, float>::type>::kBytes
+                : 0;
 }
 
 int launch_sweep(art_ctx* c, const SweepArgs& a, int level, int mode) {
@@ -1179,12 +1249,13 @@ int launch_sweep(art_ctx* c, const SweepArgs& a, int level, int mode) {
 int launch_adjoint(art_ctx* c, const AdjArgs& a, int level) {
     const dim3 grid((unsigned)(c->cu_count * c->o.blocks_per_cu)), block((unsigned)c->o.block_size);
     const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
+    const size_t lds = det ? adjoint_lds_bytes<1, true>(block.x) : adjoint_lds_bytes<1, false>(block.x);
     if (c->p.n_bins == 1) {
-        if (det) hipLaunchKernelGGL((k_adjoint<1, true>), grid, block, 0, c->stream, a, level);
-        else hipLaunchKernelGGL((k_adjoint<1, false>), grid, block, 0, c->stream, a, level);
+        if (det) hipLaunchKernelGGL((k_adjoint<1, true>), grid, block, lds, c->stream, a, level);
+        else hipLaunchKernelGGL((k_adjoint<1, false>), grid, block, lds, c->stream, a, level);
     } else {
-        if (det) hipLaunchKernelGGL((k_adjoint<2, true>), grid, block, 0, c->stream, a, level);
-        else hipLaunchKernelGGL((k_adjoint<2, false>), grid, block, 0, c->stream, a, level);
+        if (det) hipLaunchKernelGGL((k_adjoint<2, true>), grid, block, lds, c->stream, a, level);
+        else hipLaunchKernelGGL((k_adjoint<2, false>), grid, block, lds, c->stream, a, level);
     }
     HIP_TRY(hipGetLastError());
     return ART_OK;
@@ -1331,6 +1402,7 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
     if (ok) ok = det ? dmalloc(&c->det, 8 * N) : dmalloc(&c->acc, 8 * N);
     if (ok) ok = dmalloc(&c->q, N);
     if (ok && o.enable_adjoint) ok = det ? dmalloc(&c->gdet, 2 * N) : dmalloc(&c->gk, 2 * N);
+    if (ok && o.enable_adjoint) ok = dmalloc(&c->wv, N);
     if (ok) {
         c->ev.resize(2 * (ART_MAX_LEVELS + 1) * 64);
         for (auto& e : c->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
@@ -1430,14 +1502,16 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
     } else {
         if ((rc = zero(c, c->gk, 2 * N))) return rc;
     }
+    // the walk reads the packed fields; pack them again in case the tree is reused
+    hipLaunchKernelGGL(k_pack, dim3(fill_blocks(N)), dim3(256), 0, c->stream, N, n_H, x_n, c->q);
+    hipLaunchKernelGGL(k_pack_wv, dim3(fill_blocks(N)), dim3(256), 0, c->stream, N, g_rate, g_force, c->wv);
+    HIP_TRY(hipGetLastError());
     AdjArgs aa;
     aa.g = c->geo;
-    aa.nH = n_H;
-    aa.xn = x_n;
+    aa.q = c->q;
+    aa.wv = c->wv;
     aa.src_pos = src_pos;
     aa.src_lum = src_lum;
-    aa.w = g_rate;
-    aa.v = g_force;
     aa.pool = c->pool;
     aa.ct = c->ct;
     aa.gk = c->gk;

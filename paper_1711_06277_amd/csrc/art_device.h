@@ -148,86 +148,14 @@ __device__ __forceinline__ bool source_inside(const Geo& g, const double* xs) {
            xs[2] >= 0.0 && xs[2] < (double)g.nz;
 }
 
-// March one ray from r_a to r_end, cell by cell.  For every segment of positive
-// length calls visit(c, ijk[3], dr, dtau[], tau_in[]) (linear cell index, cell
-// coordinates, segment length) with the optical depth of each
-// bin over the segment and from the source to the segment's entry; then
-// tau[] += dtau[].  Returns kTerm as soon as tau_b > tau_term in every bin,
-// kSplit / kExit on reaching r_end.  *stuck is set if the traversal failed to
-// advance (non-finite input); the step count is bounded by the grid size, so
-// every lane terminates.
-template <int NB, class Visit>
-__device__ inline int march(const Geo& g, const float* __restrict__ nH, const float* __restrict__ xn,
-                            const Ray& r, double (&tau)[NB], bool* stuck, Visit&& visit) {
-    int cell[3];
-    double tnext[3];
-    const int dims[3] = {g.nx, g.ny, g.nz};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double p = r.xs[a] + r.r_a * r.n[a];
-        int c = (int)floor(p);
-        c = c < 0 ? 0 : (c > dims[a] - 1 ? dims[a] - 1 : c);
-        cell[a] = c;
-        if (r.n[a] > 0.0) tnext[a] = ((double)(c + 1) - r.xs[a]) * r.inv[a];
-        else if (r.n[a] < 0.0) tnext[a] = ((double)c - r.xs[a]) * r.inv[a];
-        else tnext[a] = INFINITY;
-    }
-    double rr = r.r_a;
-    const int max_steps = g.nx + g.ny + g.nz + 8;
-    for (int it = 0; it < max_steps; ++it) {
-        double rb = fmin(fmin(tnext[0], tnext[1]), tnext[2]);
-        const bool ends = !(rb < r.r_end);
-        if (ends) rb = r.r_end;
-        const double dr = rb - rr;
-        if (dr > 0.0) {
-            const uint32_t c = ((uint32_t)cell[2] * (uint32_t)g.ny + (uint32_t)cell[1]) * (uint32_t)g.nx +
-                               (uint32_t)cell[0];
-            const double dnH = (double)nH[c];
-            double kap[NB];
-            kap[0] = dnH * ((double)xn[c] * g.s_H + g.s_d);
-            if (NB > 1) kap[NB - 1] = dnH * g.s_d;
-            double dtau[NB];
-            bool thick = true;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) dtau[b] = kap[b] * dr;
-            visit(c, cell, dr, dtau, tau);
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                tau[b] += dtau[b];
-                thick = thick && (tau[b] > g.tau_term);
-            }
-            if (thick) return kTerm;
-            rr = rb;
-        }
-        if (ends) return r.can_split ? kSplit : kExit;
-        bool moved = false;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (tnext[a] == rb) {
-                moved = true;
-                if (r.n[a] > 0.0) {
-                    cell[a] += 1;
-                    if (cell[a] >= dims[a]) return kExit;  // rounding guard at the boundary
-                    tnext[a] = ((double)(cell[a] + 1) - r.xs[a]) * r.inv[a];
-                } else {
-                    cell[a] -= 1;
-                    if (cell[a] < 0) return kExit;
-                    tnext[a] = ((double)cell[a] - r.xs[a]) * r.inv[a];
-                }
-            }
-        }
-        if (!moved) {
-            *stuck = true;
-            return kExit;
-        }
-    }
-    *stuck = true;
-    return kExit;
-}
-
-// The same traversal as march(), one segment per call, for loops that keep
-// the whole wavefront converged between segments (the forward sweep flushes
-// its deposit staging in converged code after every step).  The (n_H, x_n)
+// Amanatides-Woo traversal of one ray from r_a to r_end, one segment per call,
+// for loops that keep the whole wavefront converged between segments (the
+// sweeps flush their deposit staging in converged code after every step).
+// tau[] accumulates the optical depth of each bin from the source; the ray ends
+// with kTerm as soon as tau_b > tau_term in every bin, else with kSplit / kExit
+// on reaching r_end.  *stuck is set if the traversal failed to advance
+// (non-finite input); the step count is bounded by the grid size, so every lane
+// terminates.  The (n_H, x_n)
 // pair of the next cell is loaded as soon as the ray steps into it, so the
 // gather's latency overlaps the current segment's deposit.
 struct MarchState {
