@@ -229,3 +229,46 @@ def random_adjoint_weights(n_cells: int, seed: int):
     w = rw.uniform(0.0, 1.0, size=n_cells).astype(np.float32)
     v = rw.uniform(0.0, 1.0, size=(3, n_cells)).astype(np.float32)
     return w, np.ascontiguousarray(v)
+
+
+# Physical constants of the HII-region tests (paper Sec. 3.3.1): cgs.
+PC_CM = 3.0857e18
+SIGMA_H_CM2 = 6.3e-18        # frequency-averaged H cross section
+ALPHA_B_RTYPE = 3.02e-13     # case-B recombination coefficient of the R-type test, cm^3/s
+Q_RTYPE = 1.0e49             # ionizing photons per second
+N_H_RTYPE = 1.0e2            # cm^-3
+
+
+@dataclass
+class IonProblem:
+    """A workload plus the code units of the ionization subcycle.
+
+    Code units: the cell is the unit of length, the background density n0 the
+    unit of density, the recombination time t_rec = 1 / (alpha_B n0) the unit of
+    time, and the source's photon rate Q the unit of luminosity.  Then
+    alpha_B = 1, the optical depth per cell length is s_H n_H with
+    s_H = sigma_H dx n0, and Gamma = gamma_scale J_0 with
+    gamma_scale = sigma_H Q t_rec / dx^2."""
+
+    wl: Workload
+    alpha_B: float
+    gamma_scale: float
+    R_S: float          # dust-free Stromgren radius in cells
+    t_rec: float = 1.0
+
+
+def rtype_problem(n: int = 128, box_over_rs: float = 2.4) -> IonProblem:
+    """R-type ionization front (paper Sec. 3.3.1): uniform neutral hydrogen of
+    n_H = 100 cm^-3 around a source of Q = 1e49 photons/s at the box centre, box
+    side 2.4 R_S, no dust, one ionizing bin, x_n = 1 at t = 0."""
+    r_s_cm = (3.0 * Q_RTYPE / (4.0 * np.pi * ALPHA_B_RTYPE * N_H_RTYPE ** 2)) ** (1.0 / 3.0)
+    dx = box_over_rs * r_s_cm / n
+    t_rec = 1.0 / (ALPHA_B_RTYPE * N_H_RTYPE)
+    s_H = SIGMA_H_CM2 * dx * N_H_RTYPE
+    gamma_scale = SIGMA_H_CM2 * Q_RTYPE * t_rec / dx ** 2
+    N = n ** 3
+    wl = Workload(name=f"R-type front {n}^3", nx=n, ny=n, nz=n,
+                  n_H=np.ones(N, dtype=np.float32), x_n=np.ones(N, dtype=np.float32),
+                  src_pos=np.array([[n / 2.0, n / 2.0, n / 2.0]]),
+                  src_lum=np.ones((1, 1), dtype=np.float32), s_H=float(s_H), s_d=0.0, n_bins=1)
+    return IonProblem(wl=wl, alpha_B=1.0, gamma_scale=float(gamma_scale), R_S=r_s_cm / dx)
