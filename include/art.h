@@ -154,6 +154,51 @@ int art_autotune(art_ctx *ctx, const float *n_H, const float *x_n, const double 
 int art_set_timing(art_ctx *ctx, int enable);
 int art_get_timing(art_ctx *ctx, float *sweep_ms_total, int *sweep_launches, float *total_ms);
 
+/* ---- Ionization subcycle around the sweep (Sec. 2.3) -------------------------
+ *
+ * The source update of the neutral fraction, dx_n/dt = alpha_B n_e (1 - x_n) -
+ * x_n Gamma with n_e = n_H (1 - x_n) (Eq. e:xn), advanced in substeps between
+ * sweeps.  Units are the caller's, as long as they are consistent: alpha_B n_H is
+ * a rate per unit time, and Gamma = gamma_scale J_0 is the photoionization rate
+ * per neutral atom, where J_0 is the sweep's ionizing-bin J (so gamma_scale =
+ * s_H / V_cell, the cross-section per cell length over the cell volume). */
+typedef struct {
+    double alpha_B;      /* case-B recombination coefficient (>= 0) */
+    double gamma_scale;  /* Gamma = gamma_scale * J_0 (>= 0) */
+    double C;            /* substep coefficient of Eq. e:dtss (> 0; the paper uses 0.1) */
+} art_ion_params;
+
+/* One radiation substep (Sec. 2.3, the subcycle after the hydro update):
+ *   1. art_trace of the current x_n (rate, force and J are written as art_trace
+ *      writes them; J must hold n_bins*N floats, bin 0 being the ionizing one);
+ *   2. dt = min(C * min over cells with n_H > 0 of n_H / |I - R|, t_end - *t_now)
+ *      (Eq. e:dtss), with I = Gamma n_H x_n and R = alpha_B n_e^2; dt = 0 once
+ *      *t_now >= t_end;
+ *   3. x_n <- x_eq0 + (x_n - x_eq0) exp(-dt (Gamma + alpha_B n_e)), x_eq0 =
+ *      alpha_B n_e / (Gamma + alpha_B n_e), n_e from the substep's start (Method B,
+ *      Eq. e:xn3), in FP64 per cell, stored as float32 in place;
+ *   4. impulse[3][N] += force * dt if impulse is not NULL (the momentum kick of the
+ *      radiation force over the substep, in the force's units times time);
+ *   5. *t_now += dt (set to t_end exactly when the substep reaches it).
+ * t_now is a device pointer to one double.  Everything is asynchronous on the
+ * context's stream and capturable in a HIP graph (no host synchronisation, no
+ * allocation); the device status is reported by art_sync.  The dt taken can be
+ * read back from *t_now.  Errors: ART_ERR_INVALID_ARG for a NULL argument, a
+ * negative alpha_B or gamma_scale, or C <= 0; the errors of art_trace. */
+int art_ion_substep(art_ctx *ctx, const float *n_H, float *x_n, const double *src_pos,
+                    const float *src_lum, int n_src, const art_ion_params *ip, double t_end,
+                    double *t_now, float *rate, float *force, float *J, float *impulse);
+
+/* The subcycle of one hydro step: substeps from t = 0 until t_end (or until
+ * max_substeps have run), synchronising after each to read the time reached and
+ * the device status.  Writes the number of substeps and the time reached (either
+ * pointer may be NULL).  x_n, rate, force, J and impulse as in art_ion_substep;
+ * impulse (if not NULL) accumulates over the whole subcycle. */
+int art_ion_subcycle(art_ctx *ctx, const float *n_H, float *x_n, const double *src_pos,
+                     const float *src_lum, int n_src, const art_ion_params *ip, double t_end,
+                     int max_substeps, float *rate, float *force, float *J, float *impulse,
+                     int *n_substeps, double *t_reached);
+
 void art_destroy(art_ctx *ctx);
 const char *art_strerror(int code);
 

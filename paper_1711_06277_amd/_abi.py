@@ -28,7 +28,7 @@ ART_MAX_BINS = 2
 # every symbol declared in include/art.h
 EXPORTED = ("art_create", "art_set_stream", "art_trace", "art_trace_adjoint", "art_sync",
             "art_get_stats", "art_autotune", "art_set_timing", "art_get_timing",
-            "art_destroy", "art_strerror")
+            "art_ion_substep", "art_ion_subcycle", "art_destroy", "art_strerror")
 
 
 class art_params(C.Structure):
@@ -41,6 +41,10 @@ class art_options(C.Structure):
     _fields_ = [("max_sources", C.c_int), ("enable_adjoint", C.c_int),
                 ("pool_rays", C.c_int64), ("pool_mem_fraction", C.c_double),
                 ("block_size", C.c_int), ("blocks_per_cu", C.c_int)]
+
+
+class art_ion_params(C.Structure):
+    _fields_ = [("alpha_B", C.c_double), ("gamma_scale", C.c_double), ("C", C.c_double)]
 
 
 class art_stats(C.Structure):
@@ -82,6 +86,11 @@ def lib() -> C.CDLL:
         L.art_set_timing.argtypes = [vp, C.c_int]
         L.art_get_timing.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_int),
                                      C.POINTER(C.c_float)]
+        L.art_ion_substep.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.POINTER(art_ion_params),
+                                      C.c_double, vp, vp, vp, vp, vp]
+        L.art_ion_subcycle.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.POINTER(art_ion_params),
+                                       C.c_double, C.c_int, vp, vp, vp, vp, C.POINTER(C.c_int),
+                                       C.POINTER(C.c_double)]
         L.art_destroy.argtypes = [vp]
         L.art_destroy.restype = None
         L.art_strerror.argtypes = [C.c_int]
@@ -154,6 +163,21 @@ def art_get_timing(ctx):
     check(lib().art_get_timing(C.c_void_p(ctx), C.byref(s), C.byref(n), C.byref(t)),
           "art_get_timing")
     return s.value, n.value, t.value
+
+
+def art_ion_substep(ctx, n_H, x_n, src_pos, src_lum, n_src, ip: art_ion_params, t_end, t_now,
+                    rate, force, J, impulse):
+    check(lib().art_ion_substep(C.c_void_p(ctx), n_H, x_n, src_pos, src_lum, int(n_src), C.byref(ip),
+                                float(t_end), t_now, rate, force, J, impulse), "art_ion_substep")
+
+
+def art_ion_subcycle(ctx, n_H, x_n, src_pos, src_lum, n_src, ip: art_ion_params, t_end, max_substeps,
+                     rate, force, J, impulse):
+    k, t = C.c_int(), C.c_double()
+    check(lib().art_ion_subcycle(C.c_void_p(ctx), n_H, x_n, src_pos, src_lum, int(n_src), C.byref(ip),
+                                 float(t_end), int(max_substeps), rate, force, J, impulse, C.byref(k),
+                                 C.byref(t)), "art_ion_subcycle")
+    return k.value, t.value
 
 
 def art_destroy(ctx):

@@ -128,6 +128,53 @@ class ArtTracer:
             A.check(A.art_sync(self._ctx), "art_trace (device)")
         return (rate, force, J) if want_J else (rate, force)
 
+    # -- ionization subcycle (Sec. 2.3) ----------------------------------------
+    def _ion_args(self, n_H, x_n, src_pos, src_lum, out):
+        d = self.device
+        if not (isinstance(x_n, torch.Tensor) and x_n.is_cuda and x_n.dtype == torch.float32
+                and x_n.is_contiguous() and x_n.numel() == self.N):
+            raise ValueError("x_n must be a contiguous float32 device tensor of N cells (updated in place)")
+        n_H = _dev(n_H, torch.float32, d).reshape(-1)
+        if n_H.numel() != self.N:
+            raise ValueError("field size does not match the grid")
+        src_pos = _dev(src_pos, torch.float64, d).reshape(-1, 3)
+        n_src = src_pos.shape[0]
+        src_lum = _dev(src_lum, torch.float32, d).reshape(n_src, self.n_bins)
+        if out is None:
+            out = (torch.empty(self.N, dtype=torch.float32, device=d),
+                   torch.empty((3, self.N), dtype=torch.float32, device=d),
+                   torch.empty((self.n_bins, self.N), dtype=torch.float32, device=d))
+        return n_H, src_pos, n_src, src_lum, out
+
+    def ion_substep(self, n_H, x_n, src_pos, src_lum, *, alpha_B, gamma_scale, C=0.1, t_end, t_now,
+                    out=None, impulse=None, check=True):
+        """One radiation substep: sweep of the current x_n, dt = min(C min(n_H/|I-R|),
+        t_end - t_now) (Eq. e:dtss), Method B update of x_n in place (Eq. e:xn3),
+        impulse += force * dt, t_now += dt.  x_n: float32 device tensor; t_now: float64
+        device tensor of one element.  Returns (rate, force, J) of the substep's sweep."""
+        n_H, src_pos, n_src, src_lum, out = self._ion_args(n_H, x_n, src_pos, src_lum, out)
+        if not (isinstance(t_now, torch.Tensor) and t_now.is_cuda and t_now.dtype == torch.float64):
+            raise ValueError("t_now must be a float64 device tensor")
+        ip = A.art_ion_params(float(alpha_B), float(gamma_scale), float(C))
+        self._stream()
+        A.art_ion_substep(self._ctx, _ptr(n_H), _ptr(x_n), _ptr(src_pos), _ptr(src_lum), n_src, ip,
+                          float(t_end), _ptr(t_now), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]),
+                          _ptr(impulse))
+        if check:
+            A.check(A.art_sync(self._ctx), "art_ion_substep (device)")
+        return out
+
+    def ion_subcycle(self, n_H, x_n, src_pos, src_lum, *, alpha_B, gamma_scale, C=0.1, t_end,
+                     max_substeps=1000000, out=None, impulse=None):
+        """Substeps from t = 0 until t_end (synchronises after each).  Returns
+        (n_substeps, t_reached); x_n is updated in place."""
+        n_H, src_pos, n_src, src_lum, out = self._ion_args(n_H, x_n, src_pos, src_lum, out)
+        ip = A.art_ion_params(float(alpha_B), float(gamma_scale), float(C))
+        self._stream()
+        return A.art_ion_subcycle(self._ctx, _ptr(n_H), _ptr(x_n), _ptr(src_pos), _ptr(src_lum), n_src,
+                                  ip, float(t_end), int(max_substeps), _ptr(out[0]), _ptr(out[1]),
+                                  _ptr(out[2]), _ptr(impulse))
+
     def adjoint(self, n_H, x_n, src_pos, src_lum, g_rate, g_force, *, out=None, check=True):
         """dL/dn_H, dL/dx_n for L = <g_rate, rate> + <g_force, force>."""
         d = self.device

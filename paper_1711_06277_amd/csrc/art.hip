@@ -1032,6 +1032,73 @@ __global__ void k_adj_finalize(uint64_t N, const double* gk, const unsigned long
     }
 }
 
+// --------------------------------------------------------------------------
+// Ionization subcycle (Sec. 2.3): substep size and Method B update
+// --------------------------------------------------------------------------
+
+// ion[0]: min over cells of n_H / |I - R| as the bits of a non-negative double
+// (such bit patterns order like the values, so an unsigned atomic min works);
+// ion[1]: the substep's dt (bits); ion[2]: time of art_ion_subcycle's own clock.
+__global__ void k_ion_begin(unsigned long long* ion) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) ion[0] = 0x7ff0000000000000ull;  // +inf
+}
+
+__global__ void __launch_bounds__(256) k_ion_minq(uint64_t N, const float* nH, const float* xn, const float* J0,
+                                                  double gamma_scale, double alpha_B, unsigned long long* ion) {
+    __shared__ double part[256 / kWave];
+    double q = INFINITY;
+    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N; c += (uint64_t)gridDim.x * blockDim.x) {
+        const double n = (double)nH[c];
+        if (!(n > 0.0)) continue;
+        const double x = (double)xn[c];
+        const double ne = n * (1.0 - x);
+        const double I = gamma_scale * (double)J0[c] * n * x;
+        const double R = alpha_B * ne * ne;
+        const double d = fabs(I - R);
+        if (d > 0.0) q = fmin(q, n / d);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) q = fmin(q, __shfl_xor(q, o, kWave));
+    if (lane_id() == 0) part[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x / kWave); ++k) q = fmin(q, part[k]);
+        atomicMin(&ion[0], (unsigned long long)__double_as_longlong(q));
+    }
+}
+
+__global__ void k_ion_dt(unsigned long long* ion, double C, double t_end, double* t_now) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double q = __longlong_as_double((long long)ion[0]);
+    const double t = *t_now;
+    const double rem = t_end - t;
+    double dt = C * q;  // +inf if no cell changes
+    const bool last = !(dt < rem);
+    if (last) dt = rem;
+    if (!(dt > 0.0)) dt = 0.0;
+    ion[1] = (unsigned long long)__double_as_longlong(dt);
+    *t_now = (last && rem > 0.0) ? t_end : t + dt;
+}
+
+__global__ void k_ion_update(uint64_t N, const float* nH, float* xn, const float* J0, const float* force,
+                             float* impulse, double gamma_scale, double alpha_B, const unsigned long long* ion) {
+    const double dt = __longlong_as_double((long long)ion[1]);
+    if (!(dt > 0.0)) return;
+    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N; c += (uint64_t)gridDim.x * blockDim.x) {
+        const double x0 = (double)xn[c];
+        const double a = alpha_B * (double)nH[c] * (1.0 - x0);
+        const double s = gamma_scale * (double)J0[c] + a;
+        if (s > 0.0) {
+            const double xeq = a / s;
+            xn[c] = (float)(xeq + (x0 - xeq) * exp(-dt * s));
+        }
+        if (impulse) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                impulse[k * N + c] = (float)((double)impulse[k * N + c] + (double)force[k * N + c] * dt);
+        }
+    }
+}
+
 }  // namespace
 
 // --------------------------------------------------------------------------
@@ -1057,6 +1124,7 @@ struct art_ctx {
     double* gk;
     unsigned long long* gdet;
     float* fscratch;
+    unsigned long long* ion;  // [4] ionization subcycle: min n_H/|I-R| bits, dt bits, own clock
     float2* q;                // [N] packed (n_H, x_n)
     float4* wv;               // [N] packed adjoint weights (w, v_x, v_y, v_z)
     // tape of the last forward (valid only for a single-wave trace)
@@ -1177,6 +1245,7 @@ void free_all(art_ctx* c) {
     (void)hipFree(c->gk);
     (void)hipFree(c->gdet);
     (void)hipFree(c->fscratch);
+    (void)hipFree(c->ion);
     (void)hipFree(c->q);
     (void)hipFree(c->wv);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -1396,7 +1465,8 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
               dmalloc(&c->ct, 1) && dmalloc(&c->st.created, ms * ART_MAX_LEVELS) &&
               dmalloc(&c->st.split, ms * ART_MAX_LEVELS) && dmalloc(&c->st.exited, ms * ART_MAX_LEVELS) &&
               dmalloc(&c->st.term, ms * ART_MAX_LEVELS) && dmalloc(&c->st.escaped, ms * 2) &&
-              dmalloc(&c->st.residual, ms * 2) && dmalloc(&c->st.segments, ms) && dmalloc(&c->fscratch, 64);
+              dmalloc(&c->st.residual, ms * 2) && dmalloc(&c->st.segments, ms) && dmalloc(&c->fscratch, 64) &&
+              dmalloc(&c->ion, 4);
     if (ok && o.enable_adjoint)
         ok = dmalloc(&c->pool.child, cap) && dmalloc(&c->pool.G, 2 * cap);
     if (ok) ok = det ? dmalloc(&c->det, 8 * N) : dmalloc(&c->acc, 8 * N);
@@ -1674,6 +1744,48 @@ int art_autotune(art_ctx* c, const float* n_H, const float* x_n, const double* s
     if (best_bpc) *best_bpc = bp;
     if (best_ms) *best_ms = best;
     return art_sync(c);
+}
+
+int art_ion_substep(art_ctx* c, const float* n_H, float* x_n, const double* src_pos, const float* src_lum,
+                    int n_src, const art_ion_params* ip, double t_end, double* t_now, float* rate, float* force,
+                    float* J, float* impulse) {
+    if (!c || !ip || !t_now || !J) return ART_ERR_INVALID_ARG;
+    if (!(ip->alpha_B >= 0.0) || !(ip->gamma_scale >= 0.0) || !(ip->C > 0.0) || std::isnan(t_end))
+        return ART_ERR_INVALID_ARG;
+    int rc = art_trace(c, n_H, x_n, src_pos, src_lum, n_src, rate, force, J);
+    if (rc) return rc;
+    const uint64_t N = c->N;
+    const dim3 fg(fill_blocks(N)), fb(256);
+    hipLaunchKernelGGL(k_ion_begin, dim3(1), dim3(64), 0, c->stream, c->ion);
+    hipLaunchKernelGGL(k_ion_minq, fg, fb, 0, c->stream, N, n_H, (const float*)x_n, (const float*)J,
+                       ip->gamma_scale, ip->alpha_B, c->ion);
+    hipLaunchKernelGGL(k_ion_dt, dim3(1), dim3(64), 0, c->stream, c->ion, ip->C, t_end, t_now);
+    hipLaunchKernelGGL(k_ion_update, fg, fb, 0, c->stream, N, n_H, x_n, (const float*)J, (const float*)force,
+                       impulse, ip->gamma_scale, ip->alpha_B, (const unsigned long long*)c->ion);
+    HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+
+int art_ion_subcycle(art_ctx* c, const float* n_H, float* x_n, const double* src_pos, const float* src_lum,
+                     int n_src, const art_ion_params* ip, double t_end, int max_substeps, float* rate,
+                     float* force, float* J, float* impulse, int* n_substeps, double* t_reached) {
+    if (!c || !ip || max_substeps < 0 || std::isnan(t_end)) return ART_ERR_INVALID_ARG;
+    double* clock = (double*)(c->ion + 2);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->stream, clock, (uint64_t)1);
+    HIP_TRY(hipGetLastError());
+    double t = 0.0;
+    int k = 0;
+    int rc = ART_OK;
+    while (k < max_substeps && t < t_end) {
+        if ((rc = art_ion_substep(c, n_H, x_n, src_pos, src_lum, n_src, ip, t_end, clock, rate, force, J, impulse)))
+            break;
+        ++k;
+        if ((rc = art_sync(c))) break;
+        HIP_TRY(hipMemcpy(&t, clock, sizeof(double), hipMemcpyDeviceToHost));
+    }
+    if (n_substeps) *n_substeps = k;
+    if (t_reached) *t_reached = t;
+    return rc;
 }
 
 void art_destroy(art_ctx* c) {
