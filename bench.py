@@ -75,6 +75,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the one-source-per-call timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint sweep timing")
+    ap.add_argument("--no-ion", action="store_true", help="skip the ionization-subcycle timing")
     ap.add_argument("--atomic", action="store_true",
                     help="FP32 atomic deposits instead of the (faster) 64-bit fixed-point ones")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -247,6 +248,76 @@ def main():
             f"({segments / adj_s:.3e} segments/s), forward with tree "
             f"{1e3 * t_fwd / args.steps:.2f} ms, status {rc}")
 
+    # ---- ionization subcycle: the R-type front at 128^3 (one source, C = 0.1) from
+    #      t = 0 to 4 t_rec; eager (one synchronisation per substep) and replaying
+    #      a HIP graph of 8 substeps until the clock reaches the end ----
+    ion = None
+    if not args.no_ion:
+        if tr is not None:
+            tr.close()
+            tr = None
+        p = I.rtype_problem(128)
+        iw = p.wl
+        ti = ArtTracer(iw.nx, iw.ny, iw.nz, s_H=iw.s_H, s_d=iw.s_d, n_bins=iw.n_bins,
+                       deterministic=True, max_sources=1, device=dev)
+        inH = torch.from_numpy(iw.n_H).to(dev)
+        ipos = torch.from_numpy(iw.src_pos).to(dev)
+        ilum = torch.from_numpy(iw.src_lum).to(dev)
+        ix = torch.from_numpy(iw.x_n).to(dev)
+        kw = dict(alpha_B=p.alpha_B, gamma_scale=p.gamma_scale, C=0.1)
+        ti.ion_subcycle(inH, ix, ipos, ilum, t_end=0.01, **kw)  # warm-up
+        ix.copy_(torch.from_numpy(iw.x_n).to(dev))
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        k_eager, t_eager = ti.ion_subcycle(inH, ix, ipos, ilum, t_end=4.0, **kw)
+        torch.cuda.synchronize()
+        t_e = time.perf_counter() - te
+        r_e = (3.0 * float((ix < 0.5).sum().item()) / (4.0 * math.pi)) ** (1.0 / 3.0)
+        r_ref = p.R_S * (1.0 - math.exp(-4.0)) ** (1.0 / 3.0)
+        # graph of 8 substeps
+        N1 = iw.n_cells
+        iout = (torch.empty(N1, device=dev), torch.empty((3, N1), device=dev), torch.empty((1, N1), device=dev))
+        t_now = torch.zeros(1, dtype=torch.float64, device=dev)
+        chunk = 8
+
+        def steps():
+            for _ in range(chunk):
+                ti.ion_substep(inH, ix, ipos, ilum, t_end=4.0, t_now=t_now, out=iout, check=False, **kw)
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            steps()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            steps()
+        ix.copy_(torch.from_numpy(iw.x_n).to(dev))
+        t_now.zero_()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        replays = 0
+        while float(t_now.item()) < 4.0 and replays < 100000:
+            g.replay()
+            replays += 1
+        torch.cuda.synchronize()
+        t_g = time.perf_counter() - tg
+        rc = ti.sync()
+        del g
+        r_g = (3.0 * float((ix < 0.5).sum().item()) / (4.0 * math.pi)) ** (1.0 / 3.0)
+        ti.close()
+        ion = {"workload": "R-type front: 128^3 uniform n_H, one central source, Method B, C = 0.1, "
+                           "t = 0 to 4 t_rec",
+               "substeps": k_eager, "eager_ms": 1e3 * t_e, "eager_ms_per_substep": 1e3 * t_e / max(1, k_eager),
+               "graph_substeps_run": replays * chunk, "graph_ms": 1e3 * t_g,
+               "graph_ms_per_substep": 1e3 * t_g / max(1, replays * chunk),
+               "front_radius_rel_err_eager": r_e / r_ref - 1.0, "front_radius_rel_err_graph": r_g / r_ref - 1.0,
+               "status": rc}
+        log(f"[bench] ion subcycle: {k_eager} substeps to 4 t_rec, eager {1e3 * t_e:.1f} ms "
+            f"({1e3 * t_e / max(1, k_eager):.3f} ms/substep), graph {1e3 * t_g:.1f} ms for "
+            f"{replays * chunk} substeps; front radius {r_e / r_ref - 1:+.4f} vs analytic")
+
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device=dev)
@@ -295,6 +366,7 @@ def main():
                    "segments_per_trace": segments, "waves": st.n_waves},
         "plain": plain,
         "adjoint": adjoint,
+        "ion_subcycle": ion,
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic / 1e9,
