@@ -1117,6 +1117,8 @@ struct art_ctx {
     Pool pool;
     uint64_t per_src_bound;
     int wave_max;
+    int cur_wave = 1;           // sources in the wave being swept (sizes the shallow levels' grids)
+    int deepest;                // deepest level that can hold rays in this grid
     Counters* ct;
     SrcStats st;
     float* acc;              // [8][N] AoS deposit accumulator (atomic mode)
@@ -1210,6 +1212,16 @@ uint64_t rays_bound_per_source(int nx, int ny, int nz, const art_params& p) {
     return tot;
 }
 
+// Level l holds rays only if its parents could split, i.e. if r_max(l-1) is
+// below the largest distance from a source inside the box to a point of it (at
+// most the box diagonal); deeper levels stay empty and are not launched.
+int deepest_level(int nx, int ny, int nz, const art_params& p) {
+    const double diag = sqrt((double)nx * nx + (double)ny * ny + (double)nz * nz);
+    int l = p.level0;
+    while (l < p.level_max && r_max_host(p.phi_c, l) < diag) ++l;
+    return l;
+}
+
 int check_params(const art_params* p) {
     if (!p) return ART_ERR_INVALID_ARG;
     if (p->level0 < 0 || p->level_max < p->level0 || p->level_max >= ART_MAX_LEVELS) return ART_ERR_INVALID_ARG;
@@ -1289,8 +1301,23 @@ size_t sweep_lds_bytes(unsigned block) {
                 : 0;
 }
 
+// At most n_wave * 12 * 4^l rays exist at level l (and no more than the pool
+// holds): shallow levels of a few sources get a grid that fits their rays
+// instead of the full resident grid, whose idle workgroups would only add
+// launch time.
+uint64_t level_rays_bound(const art_ctx* c, int level) {
+    const uint64_t all = (12ull << (2 * level)) * (uint64_t)std::max(1, c->cur_wave);
+    return std::min<uint64_t>(all, c->pool.cap);
+}
+
+unsigned level_blocks(const art_ctx* c, int level) {
+    const uint64_t full = (uint64_t)c->cu_count * (uint64_t)c->o.blocks_per_cu;
+    const uint64_t need = (level_rays_bound(c, level) + c->o.block_size - 1) / c->o.block_size;
+    return (unsigned)std::max<uint64_t>(1, std::min(full, need));
+}
+
 int launch_sweep(art_ctx* c, const SweepArgs& a, int level, int mode) {
-    const dim3 grid((unsigned)(c->cu_count * c->o.blocks_per_cu)), block((unsigned)c->o.block_size);
+    const dim3 grid(level_blocks(c, level)), block((unsigned)c->o.block_size);
     const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
     const int nb = c->p.n_bins;
     const bool tm = c->timing && c->ev_used + 2 <= (int)c->ev.size();
@@ -1316,7 +1343,7 @@ int launch_sweep(art_ctx* c, const SweepArgs& a, int level, int mode) {
 }
 
 int launch_adjoint(art_ctx* c, const AdjArgs& a, int level) {
-    const dim3 grid((unsigned)(c->cu_count * c->o.blocks_per_cu)), block((unsigned)c->o.block_size);
+    const dim3 grid(level_blocks(c, level)), block((unsigned)c->o.block_size);
     const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
     const size_t lds = det ? adjoint_lds_bytes<1, true>(block.x) : adjoint_lds_bytes<1, false>(block.x);
     if (c->p.n_bins == 1) {
@@ -1331,6 +1358,7 @@ int launch_adjoint(art_ctx* c, const AdjArgs& a, int level) {
 }
 
 int seed_wave(art_ctx* c, int s0, int n_wave) {
+    c->cur_wave = n_wave;
     const uint64_t n = (uint64_t)(12ull << (2 * c->p.level0)) * (uint64_t)n_wave;
     hipLaunchKernelGGL(k_seed, dim3(fill_blocks(n)), dim3(256), 0, c->stream, c->pool, c->ct, c->p.level0, s0,
                        n_wave, c->p.n_bins, c->pool.child ? 1 : 0);
@@ -1341,7 +1369,8 @@ int seed_wave(art_ctx* c, int s0, int n_wave) {
 // Sweep every level of the current wave, l0 first.
 // Children of level l, in parent order (see k_split_count).
 int split_level(art_ctx* c, int l) {
-    const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(4096, (c->pool.cap + kSplitTile - 1) / kSplitTile));
+    const uint64_t tiles = (level_rays_bound(c, l) + kSplitTile - 1) / kSplitTile;
+    const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(4096, tiles));
     hipLaunchKernelGGL(k_split_count, dim3(blocks), dim3(kSplitThreads), 0, c->stream, c->pool, c->ct, l);
     hipLaunchKernelGGL(k_split_scan, dim3(1), dim3(1024), 0, c->stream, c->pool, c->ct, l);
     hipLaunchKernelGGL(k_split_scatter, dim3(blocks), dim3(kSplitThreads), 0, c->stream, c->pool, c->ct, l);
@@ -1350,10 +1379,10 @@ int split_level(art_ctx* c, int l) {
 }
 
 int sweep_wave(art_ctx* c, const SweepArgs& a, int mode) {
-    for (int l = c->p.level0; l <= c->p.level_max; ++l) {
+    for (int l = c->p.level0; l <= c->deepest; ++l) {
         int rc = launch_sweep(c, a, l, mode);
         if (rc) return rc;
-        if (l < c->p.level_max && (rc = split_level(c, l))) return rc;
+        if (l < c->deepest && (rc = split_level(c, l))) return rc;
     }
     hipLaunchKernelGGL(k_end_wave, dim3(1), dim3(64), 0, c->stream, c->ct, c->p.level0, c->p.level_max);
     HIP_TRY(hipGetLastError());
@@ -1435,6 +1464,7 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
 
     // ray pool
     c->per_src_bound = rays_bound_per_source(nx, ny, nz, *params);
+    c->deepest = deepest_level(nx, ny, nz, *params);
     const uint64_t bytes_per_ray = 4 + 4 + 16 + 16 + (o.enable_adjoint ? 4 + 16 : 0);
     uint64_t cap = (uint64_t)o.pool_rays;
     if (cap == 0) {
@@ -1589,7 +1619,7 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
     aa.N = (uint32_t)N;
     aa.n_src = (uint32_t)n_src;
     if (reuse) {
-        for (int l = c->p.level_max; l >= c->p.level0; --l)
+        for (int l = c->deepest; l >= c->p.level0; --l)
             if ((rc = launch_adjoint(c, aa, l))) return rc;
     } else {
         // rebuild the tree wave by wave (tau recomputed, no segment storage)
@@ -1605,7 +1635,7 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
             const int nw = std::min(c->wave_max, n_src - s0);
             if ((rc = seed_wave(c, s0, nw))) return rc;
             if ((rc = sweep_wave(c, a, 0))) return rc;
-            for (int l = c->p.level_max; l >= c->p.level0; --l)
+            for (int l = c->deepest; l >= c->p.level0; --l)
                 if ((rc = launch_adjoint(c, aa, l))) return rc;
         }
         c->last_nsrc = n_src;
