@@ -154,6 +154,29 @@ int art_autotune(art_ctx *ctx, const float *n_H, const float *x_n, const double 
 int art_set_timing(art_ctx *ctx, int enable);
 int art_get_timing(art_ctx *ctx, float *sweep_ms_total, int *sweep_launches, float *total_ms);
 
+/* ---- Rotation of the ray directions (Sec. 2.1) --------------------------------
+ *
+ * Every HEALPix direction is multiplied by a rotation before it is traced; the
+ * paper rotates the injection directions at random every time step to smear the
+ * geometric artefacts of the crossing-length deposit.  The rotation lives in
+ * device memory: it starts as art_params.rot and applies to every later
+ * art_trace / art_trace_adjoint / art_ion_substep on the context (an adjoint whose
+ * forward tree was traced under another rotation retraces the tree). */
+
+/* Set the rotation (host array of 9 doubles, row-major; rows orthonormal within
+ * 1e-6, else ART_ERR_INVALID_ARG).  Asynchronous on the context's stream. */
+int art_set_rotation(art_ctx *ctx, const double *rot);
+
+/* Set a uniformly distributed (Haar) random rotation drawn from u, a device
+ * pointer to three numbers in [0, 1) supplied by the caller: the unit quaternion
+ * (sqrt(1-u0) sin 2 pi u1, sqrt(1-u0) cos 2 pi u1, sqrt(u0) sin 2 pi u2,
+ * sqrt(u0) cos 2 pi u2) of Shoemake's construction.  Asynchronous and
+ * graph-capturable: a captured call reads u when the graph runs. */
+int art_random_rotation(art_ctx *ctx, const double *u);
+
+/* Synchronise the stream and copy the current rotation to rot (host, 9 doubles). */
+int art_get_rotation(art_ctx *ctx, double *rot);
+
 /* ---- Ionization subcycle around the sweep (Sec. 2.3) -------------------------
  *
  * The source update of the neutral fraction, dx_n/dt = alpha_B n_e (1 - x_n) -

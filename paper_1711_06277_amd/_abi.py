@@ -28,6 +28,7 @@ ART_MAX_BINS = 2
 # every symbol declared in include/art.h
 EXPORTED = ("art_create", "art_set_stream", "art_trace", "art_trace_adjoint", "art_sync",
             "art_get_stats", "art_autotune", "art_set_timing", "art_get_timing",
+            "art_set_rotation", "art_random_rotation", "art_get_rotation",
             "art_ion_substep", "art_ion_subcycle", "art_destroy", "art_strerror")
 
 
@@ -86,6 +87,9 @@ def lib() -> C.CDLL:
         L.art_set_timing.argtypes = [vp, C.c_int]
         L.art_get_timing.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_int),
                                      C.POINTER(C.c_float)]
+        L.art_set_rotation.argtypes = [vp, C.POINTER(C.c_double)]
+        L.art_random_rotation.argtypes = [vp, vp]
+        L.art_get_rotation.argtypes = [vp, C.POINTER(C.c_double)]
         L.art_ion_substep.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.POINTER(art_ion_params),
                                       C.c_double, vp, vp, vp, vp, vp]
         L.art_ion_subcycle.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.POINTER(art_ion_params),
@@ -163,6 +167,21 @@ def art_get_timing(ctx):
     check(lib().art_get_timing(C.c_void_p(ctx), C.byref(s), C.byref(n), C.byref(t)),
           "art_get_timing")
     return s.value, n.value, t.value
+
+
+def art_set_rotation(ctx, rot):
+    r = (C.c_double * 9)(*[float(x) for x in rot])
+    check(lib().art_set_rotation(C.c_void_p(ctx), r), "art_set_rotation")
+
+
+def art_random_rotation(ctx, u):
+    check(lib().art_random_rotation(C.c_void_p(ctx), u), "art_random_rotation")
+
+
+def art_get_rotation(ctx):
+    r = (C.c_double * 9)()
+    check(lib().art_get_rotation(C.c_void_p(ctx), r), "art_get_rotation")
+    return list(r)
 
 
 def art_ion_substep(ctx, n_H, x_n, src_pos, src_lum, n_src, ip: art_ion_params, t_end, t_now,

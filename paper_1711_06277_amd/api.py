@@ -128,6 +128,25 @@ class ArtTracer:
             A.check(A.art_sync(self._ctx), "art_trace (device)")
         return (rate, force, J) if want_J else (rate, force)
 
+    # -- rotation of the ray directions (Sec. 2.1) ------------------------------
+    def set_rotation(self, rot):
+        """Rotate every ray direction by rot (3x3, orthonormal) from the next call on."""
+        self._stream()
+        A.art_set_rotation(self._ctx, np.asarray(rot, dtype=np.float64).reshape(9))
+
+    def random_rotation(self, u):
+        """Draw a uniform random rotation on the device from u, a float64 device tensor
+        of three numbers in [0, 1) (graph-capturable: u is read when the call runs)."""
+        if not (isinstance(u, torch.Tensor) and u.is_cuda and u.dtype == torch.float64 and u.numel() >= 3
+                and u.is_contiguous()):
+            raise ValueError("u must be a contiguous float64 device tensor of 3 numbers")
+        self._stream()
+        A.art_random_rotation(self._ctx, _ptr(u))
+
+    def rotation(self) -> np.ndarray:
+        """The current rotation (synchronises)."""
+        return np.array(A.art_get_rotation(self._ctx)).reshape(3, 3)
+
     # -- ionization subcycle (Sec. 2.3) ----------------------------------------
     def _ion_args(self, n_H, x_n, src_pos, src_lum, out):
         d = self.device

@@ -1099,6 +1099,39 @@ __global__ void k_ion_update(uint64_t N, const float* nH, float* xn, const float
     }
 }
 
+// --------------------------------------------------------------------------
+// Rotation of the ray directions (Sec. 2.1: random at every time step)
+// --------------------------------------------------------------------------
+
+struct Mat3 {
+    double m[9];
+};
+
+__global__ void k_set_rot(Mat3 r, double* rot) {
+    if (threadIdx.x < 9 && blockIdx.x == 0) rot[threadIdx.x] = r.m[threadIdx.x];
+}
+
+// Uniform (Haar) random rotation from three uniform numbers (Shoemake's
+// quaternion construction): q = (sqrt(1-u1) sin 2pi u2, sqrt(1-u1) cos 2pi u2,
+// sqrt(u1) sin 2pi u3, sqrt(u1) cos 2pi u3) = (x, y, z, w) and its matrix.
+__global__ void k_random_rot(const double* u, double* rot) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double u1 = u[0], a = sqrt(1.0 - u1), b = sqrt(u1);
+    double s2, c2, s3, c3;
+    sincos(2.0 * M_PI * u[1], &s2, &c2);
+    sincos(2.0 * M_PI * u[2], &s3, &c3);
+    const double x = a * s2, y = a * c2, z = b * s3, w = b * c3;
+    rot[0] = 1.0 - 2.0 * (y * y + z * z);
+    rot[1] = 2.0 * (x * y - z * w);
+    rot[2] = 2.0 * (x * z + y * w);
+    rot[3] = 2.0 * (x * y + z * w);
+    rot[4] = 1.0 - 2.0 * (x * x + z * z);
+    rot[5] = 2.0 * (y * z - x * w);
+    rot[6] = 2.0 * (x * z - y * w);
+    rot[7] = 2.0 * (y * z + x * w);
+    rot[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
 }  // namespace
 
 // --------------------------------------------------------------------------
@@ -1127,6 +1160,7 @@ struct art_ctx {
     unsigned long long* gdet;
     float* fscratch;
     unsigned long long* ion;  // [4] ionization subcycle: min n_H/|I-R| bits, dt bits, own clock
+    double* rot;              // [9] rotation of the ray directions read by the sweeps
     float2* q;                // [N] packed (n_H, x_n)
     float4* wv;               // [N] packed adjoint weights (w, v_x, v_y, v_z)
     // tape of the last forward (valid only for a single-wave trace)
@@ -1258,6 +1292,7 @@ void free_all(art_ctx* c) {
     (void)hipFree(c->gdet);
     (void)hipFree(c->fscratch);
     (void)hipFree(c->ion);
+    (void)hipFree(c->rot);
     (void)hipFree(c->q);
     (void)hipFree(c->wv);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -1459,7 +1494,7 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
     g.tau_term = params->tau_term;
     g.s_H = params->s_H;
     g.s_d = params->s_d;
-    for (int i = 0; i < 9; ++i) g.rot[i] = params->rot[i];
+    g.rot = nullptr;  // set once the device copy exists
     for (int l = 0; l < ART_MAX_LEVELS; ++l) g.rmax[l] = r_max_host(params->phi_c, l);
 
     // ray pool
@@ -1496,7 +1531,7 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
               dmalloc(&c->st.split, ms * ART_MAX_LEVELS) && dmalloc(&c->st.exited, ms * ART_MAX_LEVELS) &&
               dmalloc(&c->st.term, ms * ART_MAX_LEVELS) && dmalloc(&c->st.escaped, ms * 2) &&
               dmalloc(&c->st.residual, ms * 2) && dmalloc(&c->st.segments, ms) && dmalloc(&c->fscratch, 64) &&
-              dmalloc(&c->ion, 4);
+              dmalloc(&c->ion, 4) && dmalloc(&c->rot, 9);
     if (ok && o.enable_adjoint)
         ok = dmalloc(&c->pool.child, cap) && dmalloc(&c->pool.G, 2 * cap);
     if (ok) ok = det ? dmalloc(&c->det, 8 * N) : dmalloc(&c->acc, 8 * N);
@@ -1514,6 +1549,12 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
         (void)hipGetLastError();
         return ART_ERR_OUT_OF_MEMORY;
     }
+    if (hipMemcpy(c->rot, params->rot, 9 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return ART_ERR_HIP;
+    }
+    c->geo.rot = c->rot;
     *out = c;
     return ART_OK;
 }
@@ -1774,6 +1815,39 @@ int art_autotune(art_ctx* c, const float* n_H, const float* x_n, const double* s
     if (best_bpc) *best_bpc = bp;
     if (best_ms) *best_ms = best;
     return art_sync(c);
+}
+
+int art_set_rotation(art_ctx* c, const double* rot) {
+    if (!c || !rot) return ART_ERR_INVALID_ARG;
+    Mat3 r;
+    for (int i = 0; i < 9; ++i) {
+        if (!std::isfinite(rot[i])) return ART_ERR_INVALID_ARG;
+        r.m[i] = rot[i];
+    }
+    for (int i = 0; i < 3; ++i)  // rows orthonormal within 1e-6
+        for (int j = 0; j < 3; ++j) {
+            const double d = rot[3 * i] * rot[3 * j] + rot[3 * i + 1] * rot[3 * j + 1] + rot[3 * i + 2] * rot[3 * j + 2];
+            if (fabs(d - (i == j ? 1.0 : 0.0)) > 1e-6) return ART_ERR_INVALID_ARG;
+        }
+    hipLaunchKernelGGL(k_set_rot, dim3(1), dim3(64), 0, c->stream, r, c->rot);
+    HIP_TRY(hipGetLastError());
+    c->tape_ok = false;
+    return ART_OK;
+}
+
+int art_random_rotation(art_ctx* c, const double* u) {
+    if (!c || !u) return ART_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_random_rot, dim3(1), dim3(64), 0, c->stream, u, c->rot);
+    HIP_TRY(hipGetLastError());
+    c->tape_ok = false;
+    return ART_OK;
+}
+
+int art_get_rotation(art_ctx* c, double* rot) {
+    if (!c || !rot) return ART_ERR_INVALID_ARG;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(rot, c->rot, 9 * sizeof(double), hipMemcpyDeviceToHost));
+    return ART_OK;
 }
 
 int art_ion_substep(art_ctx* c, const float* n_H, float* x_n, const double* src_pos, const float* src_lum,

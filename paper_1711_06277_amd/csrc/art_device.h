@@ -34,7 +34,7 @@ struct Geo {
     int nx, ny, nz;
     int level0, level_max, n_bins;
     double tau_term, s_H, s_d;
-    double rot[9];
+    const double* rot;            // device [9], row-major rotation of the HEALPix directions
     double rmax[ART_MAX_LEVELS];  // r_max(l) = sqrt(3/(pi m_ray)) 2^l
 };
 
