@@ -148,12 +148,24 @@ def ray_segments(shape, xs, n, r_a, r_end, cap=100000):
     return cells[:m].copy(), drs[:m].copy()
 
 
+def _transparent(n_H, transparent):
+    """Sink control volumes (Sec. 4.1: radiation does not interact with the gas in
+    them): the cells flagged in ``transparent`` neither absorb nor receive the
+    absorbed photons, which is the sweep with no gas there."""
+    nH = _f64(n_H).reshape(-1)
+    if transparent is None:
+        return nH
+    return np.where(np.asarray(transparent).reshape(-1) != 0, 0.0, nH)
+
+
 def trace(nx, ny, nz, n_H, x_n, src_pos, src_lum, *, s_H, s_d, n_bins, level0=2,
-          level_max=13, phi_c=4.0, tau_term=float(np.log(1e10)), rot=None) -> OracleResult:
-    """Forward ART sweep in FP64 (see art_oracle.c for the definition)."""
+          level_max=13, phi_c=4.0, tau_term=float(np.log(1e10)), rot=None,
+          transparent=None) -> OracleResult:
+    """Forward ART sweep in FP64 (see art_oracle.c for the definition).
+    ``transparent``: optional per-cell flags of sink control volumes."""
     lib = _load()
     N = int(nx) * int(ny) * int(nz)
-    nH = _f64(n_H).reshape(-1)
+    nH = _transparent(n_H, transparent)
     xn = _f64(x_n).reshape(-1)
     pos = _f64(src_pos).reshape(-1, 3)
     ns = pos.shape[0]
@@ -201,8 +213,18 @@ def tangent(nx, ny, nz, n_H, x_n, dn_H, dx_n, src_pos, src_lum, *, s_H, s_d, n_b
 
 
 def adjoint(nx, ny, nz, n_H, x_n, src_pos, src_lum, w, v, *, s_H, s_d, n_bins, level0=2,
-            level_max=13, phi_c=4.0, tau_term=float(np.log(1e10)), rot=None):
-    """(dL/dn_H, dL/dx_n) for L = sum w*rate + sum v.force, ray tree held fixed."""
+            level_max=13, phi_c=4.0, tau_term=float(np.log(1e10)), rot=None, transparent=None):
+    """(dL/dn_H, dL/dx_n) for L = sum w*rate + sum v.force, ray tree held fixed.
+    With ``transparent``, the outputs do not depend on the flagged cells' fields,
+    whose gradients are zero."""
+    if transparent is not None:
+        g_nH, g_xn = adjoint(nx, ny, nz, _transparent(n_H, transparent), x_n, src_pos, src_lum, w, v,
+                             s_H=s_H, s_d=s_d, n_bins=n_bins, level0=level0, level_max=level_max,
+                             phi_c=phi_c, tau_term=tau_term, rot=rot)
+        m = np.asarray(transparent).reshape(-1) != 0
+        g_nH[m] = 0.0
+        g_xn[m] = 0.0
+        return g_nH, g_xn
     lib = _load()
     N = int(nx) * int(ny) * int(nz)
     pos = _f64(src_pos).reshape(-1, 3)
