@@ -154,6 +154,17 @@ int art_autotune(art_ctx *ctx, const float *n_H, const float *x_n, const double 
 int art_set_timing(art_ctx *ctx, int enable);
 int art_get_timing(art_ctx *ctx, float *sweep_ms_total, int *sweep_launches, float *total_ms);
 
+/* ---- Sink control volumes (Sec. 4.1) -------------------------------------------
+ *
+ * Radiation does not interact with the gas inside the control volume of a star
+ * particle.  transparent is a device array of N bytes owned by the caller (nonzero =
+ * such a cell), or NULL for none; it stays in use until replaced, so it must stay
+ * valid for every later call.  In flagged cells the gas neither absorbs nor receives
+ * photons: no opacity, no rate, no force (J still holds the radiation passing
+ * through), zero gradients from art_trace_adjoint, and art_ion_substep leaves x_n
+ * unchanged and takes no substep limit from them.  Host-side only (no launch). */
+int art_set_transparent(art_ctx *ctx, const uint8_t *transparent);
+
 /* ---- Rotation of the ray directions (Sec. 2.1) --------------------------------
  *
  * Every HEALPix direction is multiplied by a rotation before it is traced; the

@@ -28,7 +28,7 @@ ART_MAX_BINS = 2
 # every symbol declared in include/art.h
 EXPORTED = ("art_create", "art_set_stream", "art_trace", "art_trace_adjoint", "art_sync",
             "art_get_stats", "art_autotune", "art_set_timing", "art_get_timing",
-            "art_set_rotation", "art_random_rotation", "art_get_rotation",
+            "art_set_transparent", "art_set_rotation", "art_random_rotation", "art_get_rotation",
             "art_ion_substep", "art_ion_subcycle", "art_destroy", "art_strerror")
 
 
@@ -87,6 +87,7 @@ def lib() -> C.CDLL:
         L.art_set_timing.argtypes = [vp, C.c_int]
         L.art_get_timing.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_int),
                                      C.POINTER(C.c_float)]
+        L.art_set_transparent.argtypes = [vp, vp]
         L.art_set_rotation.argtypes = [vp, C.POINTER(C.c_double)]
         L.art_random_rotation.argtypes = [vp, vp]
         L.art_get_rotation.argtypes = [vp, C.POINTER(C.c_double)]
@@ -167,6 +168,10 @@ def art_get_timing(ctx):
     check(lib().art_get_timing(C.c_void_p(ctx), C.byref(s), C.byref(n), C.byref(t)),
           "art_get_timing")
     return s.value, n.value, t.value
+
+
+def art_set_transparent(ctx, mask):
+    check(lib().art_set_transparent(C.c_void_p(ctx), mask), "art_set_transparent")
 
 
 def art_set_rotation(ctx, rot):

@@ -128,6 +128,20 @@ class ArtTracer:
             A.check(A.art_sync(self._ctx), "art_trace (device)")
         return (rate, force, J) if want_J else (rate, force)
 
+    # -- sink control volumes (Sec. 4.1) ----------------------------------------
+    def set_transparent(self, mask):
+        """Flag cells where radiation does not interact with the gas (a uint8 or bool
+        device tensor of N cells, kept referenced here), or None to clear."""
+        if mask is None:
+            self._transparent = None
+            A.art_set_transparent(self._ctx, None)
+            return
+        if not (isinstance(mask, torch.Tensor) and mask.is_cuda and mask.numel() == self.N):
+            raise ValueError("mask must be a device tensor of N cells")
+        m = mask.reshape(-1).to(torch.uint8).contiguous()
+        self._transparent = m
+        A.art_set_transparent(self._ctx, _ptr(m))
+
     # -- rotation of the ray directions (Sec. 2.1) ------------------------------
     def set_rotation(self, rot):
         """Rotate every ray direction by rot (3x3, orthonormal) from the next call on."""

@@ -158,10 +158,12 @@ __global__ void k_fill_f64(double* p, uint64_t n) {
 }
 
 // Interleave (n_H, x_n) so that the sweep gathers one 8-byte word per segment.
-__global__ void k_pack(uint64_t N, const float* nH, const float* xn, float2* q) {
+// transparent (optional): cells of sink control volumes, where radiation does not
+// interact with the gas (no gas as far as the sweep is concerned).
+__global__ void k_pack(uint64_t N, const float* nH, const float* xn, const uint8_t* transparent, float2* q) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N;
          i += (uint64_t)gridDim.x * blockDim.x)
-        q[i] = make_float2(nH[i], xn[i]);
+        q[i] = make_float2((transparent && transparent[i]) ? 0.0f : nH[i], xn[i]);
 }
 
 // The adjoint's per-cell weights in one 16-byte gather: (w, v_x, v_y, v_z).
@@ -795,9 +797,9 @@ __global__ void k_end_wave(Counters* ct, int level0, int level_max) {
 // rate = s_H x_n n_H J_0 (Eq. e:photrate2); force and J from the AoS
 // accumulator (stride LPE), unpacking fixed point in deterministic mode.
 template <bool DET>
-__global__ void k_finalize(uint64_t N, const float* nH, const float* xn, double s_H, const float* acc,
-                           const unsigned long long* det, int lpe, const Counters* ct, float* rate, float* force,
-                           float* J, int n_bins) {
+__global__ void k_finalize(uint64_t N, const float* nH, const float* xn, const uint8_t* transparent, double s_H,
+                           const float* acc, const unsigned long long* det, int lpe, const Counters* ct, float* rate,
+                           float* force, float* J, int n_bins) {
     const double inv = DET ? ct->c.inv_scale : 0.0;
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N;
          c += (uint64_t)gridDim.x * blockDim.x) {
@@ -810,7 +812,8 @@ __global__ void k_finalize(uint64_t N, const float* nH, const float* xn, double 
             }
             v[f] = DET ? (double)(long long)det[c * lpe + f] * inv : (double)acc[c * lpe + f];
         }
-        rate[c] = (float)(s_H * (double)xn[c] * (double)nH[c] * v[0]);
+        const double gas = (transparent && transparent[c]) ? 0.0 : (double)nH[c];
+        rate[c] = (float)(s_H * (double)xn[c] * gas * v[0]);
         force[c] = (float)v[1];
         force[N + c] = (float)v[2];
         force[2 * N + c] = (float)v[3];
@@ -1018,11 +1021,14 @@ size_t adjoint_lds_bytes(unsigned block) {
 // Convert the accumulated dL/dn_H and dL/dx_n to the FP32 outputs.
 template <bool DET>
 __global__ void k_adj_finalize(uint64_t N, const double* gk, const unsigned long long* gdet, const Counters* ct,
-                               float* g_nH, float* g_xn) {
+                               const uint8_t* transparent, float* g_nH, float* g_xn) {
     const double ginv = DET ? ct->c.inv_gscale : 0.0;
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N;
          c += (uint64_t)gridDim.x * blockDim.x) {
-        if (DET) {
+        if (transparent && transparent[c]) {  // the outputs do not depend on these fields
+            g_nH[c] = 0.0f;
+            g_xn[c] = 0.0f;
+        } else if (DET) {
             g_nH[c] = (float)((double)(long long)gdet[2 * c] * ginv);
             g_xn[c] = (float)((double)(long long)gdet[2 * c + 1] * ginv);
         } else {
@@ -1044,12 +1050,13 @@ __global__ void k_ion_begin(unsigned long long* ion) {
 }
 
 __global__ void __launch_bounds__(256) k_ion_minq(uint64_t N, const float* nH, const float* xn, const float* J0,
-                                                  double gamma_scale, double alpha_B, unsigned long long* ion) {
+                                                  const uint8_t* transparent, double gamma_scale, double alpha_B,
+                                                  unsigned long long* ion) {
     __shared__ double part[256 / kWave];
     double q = INFINITY;
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N; c += (uint64_t)gridDim.x * blockDim.x) {
         const double n = (double)nH[c];
-        if (!(n > 0.0)) continue;
+        if (!(n > 0.0) || (transparent && transparent[c])) continue;
         const double x = (double)xn[c];
         const double ne = n * (1.0 - x);
         const double I = gamma_scale * (double)J0[c] * n * x;
@@ -1080,10 +1087,12 @@ __global__ void k_ion_dt(unsigned long long* ion, double C, double t_end, double
 }
 
 __global__ void k_ion_update(uint64_t N, const float* nH, float* xn, const float* J0, const float* force,
-                             float* impulse, double gamma_scale, double alpha_B, const unsigned long long* ion) {
+                             const uint8_t* transparent, float* impulse, double gamma_scale, double alpha_B,
+                             const unsigned long long* ion) {
     const double dt = __longlong_as_double((long long)ion[1]);
     if (!(dt > 0.0)) return;
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N; c += (uint64_t)gridDim.x * blockDim.x) {
+        if (transparent && transparent[c]) continue;  // no interaction with the gas there
         const double x0 = (double)xn[c];
         const double a = alpha_B * (double)nH[c] * (1.0 - x0);
         const double s = gamma_scale * (double)J0[c] + a;
@@ -1161,6 +1170,7 @@ struct art_ctx {
     float* fscratch;
     unsigned long long* ion;  // [4] ionization subcycle: min n_H/|I-R| bits, dt bits, own clock
     double* rot;              // [9] rotation of the ray directions read by the sweeps
+    const uint8_t* transparent = nullptr;  // caller's per-cell sink flags, or none
     float2* q;                // [N] packed (n_H, x_n)
     float4* wv;               // [N] packed adjoint weights (w, v_x, v_y, v_z)
     // tape of the last forward (valid only for a single-wave trace)
@@ -1427,7 +1437,8 @@ int sweep_wave(art_ctx* c, const SweepArgs& a, int mode) {
 int begin_call(art_ctx* c, const float* lum, int n_src, const float* nH, const float* xn) {
     hipLaunchKernelGGL(k_begin_call, dim3(1), dim3(256), 0, c->stream, c->ct, lum, n_src * c->p.n_bins);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_pack, dim3(fill_blocks(c->N)), dim3(256), 0, c->stream, c->N, nH, xn, c->q);
+    hipLaunchKernelGGL(k_pack, dim3(fill_blocks(c->N)), dim3(256), 0, c->stream, c->N, nH, xn, c->transparent,
+                       c->q);
     HIP_TRY(hipGetLastError());
     return ART_OK;
 }
@@ -1600,10 +1611,12 @@ int art_trace(art_ctx* c, const float* n_H, const float* x_n, const double* src_
     }
     const dim3 fg(fill_blocks(N)), fb(256);
     if (det)
-        hipLaunchKernelGGL((k_finalize<true>), fg, fb, 0, c->stream, N, n_H, x_n, c->p.s_H, c->acc, c->det, lpe,
+        hipLaunchKernelGGL((k_finalize<true>), fg, fb, 0, c->stream, N, n_H, x_n, c->transparent, c->p.s_H, c->acc,
+                           c->det, lpe,
                            c->ct, rate, force, J, c->p.n_bins);
     else
-        hipLaunchKernelGGL((k_finalize<false>), fg, fb, 0, c->stream, N, n_H, x_n, c->p.s_H, c->acc, c->det, lpe,
+        hipLaunchKernelGGL((k_finalize<false>), fg, fb, 0, c->stream, N, n_H, x_n, c->transparent, c->p.s_H, c->acc,
+                           c->det, lpe,
                            c->ct, rate, force, J, c->p.n_bins);
     HIP_TRY(hipGetLastError());
     if (c->timing) HIP_TRY(hipEventRecord(c->ev_call1, c->stream));
@@ -1644,7 +1657,7 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
         if ((rc = zero(c, c->gk, 2 * N))) return rc;
     }
     // the walk reads the packed fields; pack them again in case the tree is reused
-    hipLaunchKernelGGL(k_pack, dim3(fill_blocks(N)), dim3(256), 0, c->stream, N, n_H, x_n, c->q);
+    hipLaunchKernelGGL(k_pack, dim3(fill_blocks(N)), dim3(256), 0, c->stream, N, n_H, x_n, c->transparent, c->q);
     hipLaunchKernelGGL(k_pack_wv, dim3(fill_blocks(N)), dim3(256), 0, c->stream, N, g_rate, g_force, c->wv);
     HIP_TRY(hipGetLastError());
     AdjArgs aa;
@@ -1684,9 +1697,11 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
     }
     const dim3 fg(fill_blocks(N)), fb(256);
     if (det)
-        hipLaunchKernelGGL((k_adj_finalize<true>), fg, fb, 0, c->stream, N, c->gk, c->gdet, c->ct, g_nH, g_xn);
+        hipLaunchKernelGGL((k_adj_finalize<true>), fg, fb, 0, c->stream, N, c->gk, c->gdet, c->ct, c->transparent,
+                           g_nH, g_xn);
     else
-        hipLaunchKernelGGL((k_adj_finalize<false>), fg, fb, 0, c->stream, N, c->gk, c->gdet, c->ct, g_nH, g_xn);
+        hipLaunchKernelGGL((k_adj_finalize<false>), fg, fb, 0, c->stream, N, c->gk, c->gdet, c->ct, c->transparent,
+                           g_nH, g_xn);
     HIP_TRY(hipGetLastError());
     return ART_OK;
 }
@@ -1817,6 +1832,13 @@ int art_autotune(art_ctx* c, const float* n_H, const float* x_n, const double* s
     return art_sync(c);
 }
 
+int art_set_transparent(art_ctx* c, const uint8_t* transparent) {
+    if (!c) return ART_ERR_INVALID_ARG;
+    c->transparent = transparent;
+    c->tape_ok = false;
+    return ART_OK;
+}
+
 int art_set_rotation(art_ctx* c, const double* rot) {
     if (!c || !rot) return ART_ERR_INVALID_ARG;
     Mat3 r;
@@ -1861,11 +1883,12 @@ int art_ion_substep(art_ctx* c, const float* n_H, float* x_n, const double* src_
     const uint64_t N = c->N;
     const dim3 fg(fill_blocks(N)), fb(256);
     hipLaunchKernelGGL(k_ion_begin, dim3(1), dim3(64), 0, c->stream, c->ion);
-    hipLaunchKernelGGL(k_ion_minq, fg, fb, 0, c->stream, N, n_H, (const float*)x_n, (const float*)J,
+    hipLaunchKernelGGL(k_ion_minq, fg, fb, 0, c->stream, N, n_H, (const float*)x_n, (const float*)J, c->transparent,
                        ip->gamma_scale, ip->alpha_B, c->ion);
     hipLaunchKernelGGL(k_ion_dt, dim3(1), dim3(64), 0, c->stream, c->ion, ip->C, t_end, t_now);
     hipLaunchKernelGGL(k_ion_update, fg, fb, 0, c->stream, N, n_H, x_n, (const float*)J, (const float*)force,
-                       impulse, ip->gamma_scale, ip->alpha_B, (const unsigned long long*)c->ion);
+                       (const uint8_t*)c->transparent, impulse, ip->gamma_scale, ip->alpha_B,
+                       (const unsigned long long*)c->ion);
     HIP_TRY(hipGetLastError());
     return ART_OK;
 }

@@ -1,0 +1,124 @@
+"""Sink control volumes (paper Sec. 4.1) and the force-only mode (Sec. 4.3) on the
+GPU against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1711_06277_amd import inputs as I
+from tests.gpu_common import compare_cells, compare_force, kappas, tree_equal
+from tests.test_oracle_transparent import cube_mask
+
+pytestmark = pytest.mark.gpu
+
+
+def tracer(wl, **kw):
+    from paper_1711_06277_amd.api import ArtTracer
+    return ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
+                     level0=wl.level0, level_max=wl.level_max, phi_c=wl.phi_c,
+                     tau_term=wl.tau_term, max_sources=max(1, wl.n_src), **kw)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def sink_mask(wl):
+    m = np.zeros(wl.n_cells, dtype=np.uint8)
+    for s in range(wl.n_src):
+        m |= cube_mask(wl.nx, wl.src_pos[s], 2.0)
+    return m
+
+
+@pytest.mark.parametrize("deterministic", [False, True])
+def test_transparent_sinks_forward_and_adjoint(oracle, deterministic):
+    """Cubes of transparent cells around every source: the forward sweep (tree bit
+    for bit, rate / J / force, zero rate and force in the cubes) and the adjoint
+    (zero gradients in the cubes) match the oracle with the same flags."""
+    wl = I.config(4, n_src=4, n=40)
+    mask = sink_mask(wl)
+    m = mask != 0
+    tr = tracer(wl, deterministic=deterministic, enable_adjoint=True)
+    try:
+        tr.set_transparent(dev(mask))
+        args = (dev(wl.n_H), dev(wl.x_n), dev(wl.src_pos), dev(wl.src_lum))
+        rate, force, J = tr.trace(*args, want_J=True)
+        st = tr.stats(wl.n_src)
+        g_nH, g_xn = tr.adjoint(*args, dev(wl.w), dev(wl.v))
+        rate, force, J = rate.cpu().numpy(), force.cpu().numpy(), J.cpu().numpy()
+        g_nH, g_xn = g_nH.cpu().numpy(), g_xn.cpu().numpy()
+        tr.set_transparent(None)
+        plain = tr.trace(*args)[0].cpu().numpy()
+    finally:
+        tr.close()
+    ref = oracle.trace_workload(wl, transparent=mask)
+    tree_equal(st, ref)
+    L = float(wl.src_lum.astype(np.float64).sum())
+    assert np.all(rate[m] == 0.0) and np.all(force[:, m] == 0.0)
+    compare_cells("rate", rate, ref.rate, L)
+    for b in range(wl.n_bins):
+        compare_cells(f"J{b}", J[b], ref.J[b], L)
+    kj = sum(k * j for k, j in zip(kappas(wl), ref.J))
+    compare_force(force, ref.force, L, kj)
+    assert not np.allclose(plain, rate)  # clearing the flags restores the gas
+    rn, rx = oracle.adjoint(wl.nx, wl.ny, wl.nz, wl.n_H, wl.x_n, wl.src_pos, wl.src_lum, wl.w, wl.v,
+                            transparent=mask, **wl.params())
+    assert np.all(g_nH[m] == 0.0) and np.all(g_xn[m] == 0.0)
+    for name, gpu, r in (("g_nH", g_nH, rn), ("g_xn", g_xn, rx)):
+        sel = np.abs(r) > 1e-6 * np.abs(r).max()
+        err = np.abs(gpu.astype(np.float64)[sel] - r[sel]) / np.abs(r[sel])
+        assert err.max() <= 1e-4, f"{name}: {err.max():.3e}"
+
+
+def test_transparent_cells_keep_their_ionization_state():
+    """An ionization substep leaves x_n of flagged cells unchanged and takes no substep
+    limit from them (the oracle's substep over the other cells)."""
+    from oracle import ion as X
+    from oracle import oracle as O
+    p = I.rtype_problem(24)
+    wl = p.wl
+    rng = np.random.default_rng(2)
+    x0 = rng.uniform(0.0, 1.0, wl.n_cells).astype(np.float32)
+    mask = cube_mask(wl.nx, wl.src_pos[0], 3.0)
+    m = mask != 0
+    ref = O.trace(wl.nx, wl.ny, wl.nz, wl.n_H, x0, wl.src_pos, wl.src_lum, s_H=wl.s_H, s_d=0.0, n_bins=1,
+                  transparent=mask)
+    G = X.gamma_from_J(ref.J[0], p.gamma_scale)
+    dt_ref = X.substep_dt(wl.n_H[~m], x0[~m], G[~m], p.alpha_B, 0.1)
+    x_ref = X.method_b(x0, wl.n_H, G, p.alpha_B, dt_ref)
+    x_ref[m] = x0[m]
+    tr = tracer(wl)
+    try:
+        tr.set_transparent(dev(mask))
+        x = dev(x0)
+        t_now = torch.zeros(1, dtype=torch.float64, device="cuda")
+        tr.ion_substep(dev(wl.n_H), x, dev(wl.src_pos), dev(wl.src_lum), alpha_B=p.alpha_B,
+                       gamma_scale=p.gamma_scale, C=0.1, t_end=10.0, t_now=t_now)
+        dt = float(t_now.item())
+        xg = x.cpu().numpy()
+    finally:
+        tr.close()
+    assert dt == pytest.approx(dt_ref, rel=1e-5)
+    assert np.array_equal(xg[m], x0[m])
+    assert np.max(np.abs(xg.astype(np.float64) - x_ref)) < 1e-5
+
+
+def test_force_only_mode_matches_oracle(oracle):
+    """Sec. 4.3's comparison run: dust only (s_H = 0), one bin: zero rate, force and J
+    to the parity bar."""
+    wl = I.config(4, n_src=3, n=32)
+    wl.s_H = 0.0
+    wl.n_bins = 1
+    wl.src_lum = np.ascontiguousarray(wl.src_lum[:, 1:2])
+    tr = tracer(wl)
+    try:
+        rate, force, J = tr.trace(dev(wl.n_H), dev(wl.x_n), dev(wl.src_pos), dev(wl.src_lum), want_J=True)
+        st = tr.stats(wl.n_src)
+        rate, force, J = rate.cpu().numpy(), force.cpu().numpy(), J.cpu().numpy()
+    finally:
+        tr.close()
+    ref = oracle.trace_workload(wl)
+    tree_equal(st, ref)
+    assert np.all(rate == 0.0)
+    L = float(wl.src_lum.astype(np.float64).sum())
+    compare_cells("J0", J[0], ref.J[0], L)
+    compare_force(force, ref.force, L, kappas(wl)[0] * ref.J[0])
