@@ -57,7 +57,7 @@ struct CallCounters {
     unsigned long long rays_wave_max;
     uint32_t status;
     uint32_t pad;
-    double scale, inv_scale;      // forward fixed point: 2^60 / L_total
+    double scale, inv_scale;      // forward fixed point: ~2^50 / L_total
     double gscale, inv_gscale;    // adjoint fixed point
 };
 
@@ -117,15 +117,12 @@ struct AdjArgs {
     uint32_t n_src;
 };
 
-// Round y (a float with |y| < 2^62) to the nearest 64-bit integer: split |y|
-// at 2^32; the low part holds only bits of |y|'s 24-bit significand, so both
-// parts are exact and convert with the 32-bit FP32 conversions.
-__device__ __forceinline__ long long fixed_point(float y) {
-    const float a = fabsf(y);
-    const float hi = floorf(a * 0x1p-32f);
-    const float lo = a - hi * 0x1p32f;  // in [0, 2^32), exact
-    const long long m = (long long)(((unsigned long long)(unsigned)hi << 32) + (unsigned long long)(unsigned)rintf(lo));
-    return y < 0.0f ? -m : m;
+// Round x * scale to the nearest 64-bit integer (ties to even), for |x * scale| <
+// 2^51: adding 1.5 * 2^52 in one FP64 rounding puts the integer in the low bits of
+// the significand (the sum stays in [2^52, 2^53), where the spacing is 1), so the
+// integer is the sum's bit pattern minus that of 1.5 * 2^52.
+__device__ __forceinline__ long long fixed_point(float x, double scale) {
+    return __double_as_longlong(fma((double)x, scale, 0x1.8p52)) - 0x4338000000000000ll;
 }
 
 
@@ -173,9 +170,8 @@ __global__ void k_pack_wv(uint64_t N, const float* w, const float* v, float4* wv
         wv[i] = make_float4(w[i], v[i], v[N + i], v[2 * N + i]);
 }
 
-// Reset the call counters; in deterministic mode also set the fixed-point
-// scale ~2^59..2^60 / L_total (a cell can receive at most ~sqrt(3) L_total of
-// J, so sums stay below 2^63).
+// Reset the call counters and set the fixed-point scale of the deterministic
+// deposits (~2^50 / L_total, a power of two).
 __global__ void k_begin_call(Counters* ct, const float* src_lum, int n_lum) {
     __shared__ double part[256];
     double s = 0.0;
@@ -192,10 +188,12 @@ __global__ void k_begin_call(Counters* ct, const float* src_lum, int n_lum) {
         ct->c.segments = 0ull;
         ct->c.rays_wave_max = 0ull;
         ct->c.status = 0u;
-        // a power of two, 2^59 / L <= scale < 2^60 / L, so that x * scale is
-        // exact in FP32 and its conversion to an integer is cheap
-        int k = 60 - ilogb(L) - 1;
-        k = k > 100 ? 100 : (k < -100 ? -100 : k);  // keep 2^k a normal FP32 number
+        // a power of two, 2^49 / L <= scale < 2^50 / L: one deposit is at most
+        // L / 12 * sqrt(3) < L / 4 (a level-0 ray across a cell), so x * scale
+        // stays below 2^48 and converts with fixed_point(); a cell's sum stays
+        // below sqrt(3) L * scale < 2^51
+        int k = 50 - ilogb(L) - 1;
+        k = k > 900 ? 900 : (k < -900 ? -900 : k);
         ct->c.scale = ldexp(1.0, k);
         ct->c.inv_scale = ldexp(1.0, -k);
     }
@@ -487,9 +485,9 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     Dep dep = Dep::at(sweep_lds + (MODE ? (size_t)w * Dep::kBytes : 0));
     if (MODE) dep.init(lane);
-    const float fscale = (float)scale;  // a power of two: x * fscale is exact
+
     auto quant = [&](float x) -> V {
-        if (DET) return (V)(unsigned long long)fixed_point(x * fscale);
+        if (DET) return (V)(unsigned long long)fixed_point(x, scale);
         else return (V)x;
     };
 
