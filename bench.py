@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint sweep timing")
     ap.add_argument("--no-ion", action="store_true", help="skip the ionization-subcycle timing")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time forward + adjoint captured in one HIP graph (adjoint leg)")
     ap.add_argument("--atomic", action="store_true",
                     help="FP32 atomic deposits instead of the (faster) 64-bit fixed-point ones")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -218,6 +220,7 @@ def main():
         ta.trace(nH, xn, pos, lum, out=out, check=False)
         ta.adjoint(nH, xn, pos, lum, w, v, out=(g_nH, g_xn), check=False)
         rc = ta.sync()
+        log("[bench] adjoint leg: warm-up done")
         t_fwd = t_adj = 0.0
         for _ in range(args.steps):
             torch.cuda.synchronize()
@@ -230,15 +233,46 @@ def main():
             ta2 = time.perf_counter()
             t_fwd += ta1 - ta0
             t_adj += ta2 - ta1
+            log(f"[bench] adjoint leg: step {1e3 * (ta1 - ta0):.1f} ms forward, {1e3 * (ta2 - ta1):.1f} ms adjoint")
         rc = rc or ta.sync()
         finite = bool(torch.isfinite(g_nH).all().item() and torch.isfinite(g_xn).all().item())
+        graph = None
+        if args.graph:
+            ref = (rate.clone(), force.clone(), g_nH.clone(), g_xn.clone())
+
+            def fwd_adj():
+                ta.trace(nH, xn, pos, lum, out=out, check=False)
+                ta.adjoint(nH, xn, pos, lum, w, v, out=(g_nH, g_xn), check=False)
+
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                fwd_adj()
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            log("[bench] graph: warm-up on the capture stream done")
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                fwd_adj()
+            torch.cuda.synchronize()
+            log("[bench] graph: captured")
+            tg0 = time.perf_counter()
+            for _ in range(args.steps):
+                g.replay()
+            torch.cuda.synchronize()
+            t_graph = (time.perf_counter() - tg0) / args.steps
+            same = all(torch.equal(a, b) for a, b in zip((rate, force, g_nH, g_xn), ref))
+            graph = {"ms_per_forward_adjoint": 1e3 * t_graph, "status": ta.sync(),
+                     "bitwise_equal_to_eager": same if wl.deterministic else None}
+            del g
+            log(f"[bench] graph forward+adjoint: {1e3 * t_graph:.2f} ms per replay, equal to eager: {same}")
         ta.close()
         adj_s = t_adj / args.steps
         adj_gbs = segments * ADJOINT_BYTES_PER_SEGMENT / adj_s / 1e9
         adjoint = {"ms_per_adjoint": 1e3 * adj_s,
                    "ms_per_forward_with_tree": 1e3 * t_fwd / args.steps,
                    "segments_per_s": segments / adj_s,
-                   "status": rc, "gradients_finite": finite,
+                   "status": rc, "gradients_finite": finite, "graph": graph,
                    "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "frac": adj_gbs / HBM_PEAK_GBS,
                                 "kernel": "k_adjoint (one launch per level, deepest first; "
