@@ -3,19 +3,23 @@
 //
 // Design (one GPU, one process):
 //   * All sources of a call share one ray pool.  Rays live in per-HEALPix-level
-//     segments of the pool, level l0 first; the children of level l are appended
-//     behind level l while it is swept, so the pool holds the whole ray tree of a
-//     source wave (and doubles as the adjoint's tape).  Sources are admitted in
-//     waves sized so that the tree of a wave fits the pool.
+//     segments of the pool, level l0 first, seeded by source and nested pixel;
+//     after level l is swept, an order-preserving scan writes the children of its
+//     splitting rays behind it in parent order, so every level stays sorted by
+//     (source, direction) and the rays in flight cover a small part of the grid.
+//     The pool holds the whole ray tree of a source wave (and doubles as the
+//     adjoint's tape).  Sources are admitted in waves sized so that the tree of a
+//     wave fits the pool.
 //   * One persistent-style launch per level: a grid of resident workgroups whose
 //     wavefronts claim 64-ray chunks from the level's shared multi-source queue
 //     with one atomic per chunk, one ray per lane.  Rays of one level have the
 //     same radial shell [r_max(l-1), r_max(l)], so the lanes of a wavefront do
 //     similar amounts of work.
 //   * Geometry, tau and all tree decisions in FP64; the per-segment deposit
-//     arithmetic in FP32; deposits by hardware FP32 atomics into L2, or by 64-bit
-//     fixed-point integer atomics in the deterministic mode (integer sums do not
-//     depend on the order, so results are bitwise reproducible).
+//     arithmetic in FP32.  Deposits are merged per wavefront in an LDS cache and
+//     flushed with coalesced global atomics: FP32, or 64-bit fixed-point integers
+//     in the deterministic mode (integer sums do not depend on the order, so
+//     results are bitwise reproducible, and LDS integer atomics are also faster).
 //   * The destroy counter of Sec. 2.2 (a ray ended at level l adds
 //     4^(l_max - l)) is kept as a device-side completeness check of the tree.
 //   * No allocation, host synchronisation or memset node inside art_trace /
@@ -45,7 +49,7 @@ namespace {
 // Counters of the current source wave, reset by the seed kernel.
 struct WaveCounters {
     uint32_t head[ART_MAX_LEVELS + 1];      // forward chunk claims per level
-    uint32_t tail[ART_MAX_LEVELS + 1];      // rays per level (children appended here)
+    uint32_t tail[ART_MAX_LEVELS + 1];      // rays per level (set by the child scan of the level above)
     uint32_t adj_head[ART_MAX_LEVELS + 1];  // adjoint chunk claims per level
     uint64_t off[ART_MAX_LEVELS + 1];       // pool offset of each level
 };
