@@ -326,8 +326,13 @@ struct Deposit {
         return Deposit{k, v, k + S, sv, 0u};
     }
 
+    // The cell's position in an 8 x 8 x 4 tile, with the tile's upper bits folded
+    // into the lower ones (a bijection): the lanes of a wavefront cross a patch of
+    // neighbouring cells, and without the fold cells that differ only in k (or in
+    // the high bit of j) would share LDS banks.
     __device__ static inline uint32_t slot(const int (&ijk)[3]) {
-        return (uint32_t)((ijk[0] & 7) | ((ijk[1] & 7) << 3) | ((ijk[2] & 3) << 6));
+        const uint32_t h = (uint32_t)((ijk[0] & 7) | ((ijk[1] & 7) << 3) | ((ijk[2] & 3) << 6));
+        return h ^ ((h >> 4) & 0xfu);
     }
     __device__ static inline void lds_add(ART_LDS float* p, float x) {
         __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -457,6 +462,37 @@ struct Deposit {
 
 // MODE 0: tree only (the tape pass of the adjoint); 1: J0 and the force;
 // 2: also J1 (the non-ionizing bin's J).  DET: 64-bit fixed-point deposits.
+// Quad pre-combine (DPP lane moves, no LDS): lanes 4k..4k+3 of a wavefront trace
+// the four children of one parent pixel and often cross the same cell in the same
+// step.  Partners lane^1 and then lane^2 compare keys; on a match the lower lane
+// adds the upper lane's values and the upper lane drops its deposit.  Same-address
+// LDS atomics serialise, so this removes most of the LDS cache's address and bank
+// conflicts for a few VALU instructions.  Converged code (every lane present).
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x, int ctrl) {
+    return ctrl == 0xB1 ? (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false)
+                        : (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);
+}
+__device__ __forceinline__ unsigned long long dpp_v(unsigned long long x, int ctrl) {
+    return ((unsigned long long)dpp_u32((uint32_t)(x >> 32), ctrl) << 32) | dpp_u32((uint32_t)x, ctrl);
+}
+__device__ __forceinline__ float dpp_v(float x, int ctrl) { return __uint_as_float(dpp_u32(__float_as_uint(x), ctrl)); }
+template <int NV, class V>
+__device__ __forceinline__ void quad_combine(int lane, uint32_t& key, V (&v)[NV]) {
+#pragma unroll
+    for (int step = 0; step < 2; ++step) {
+        const int ctrl = step == 0 ? 0xB1 : 0x4E;
+        const uint32_t kp = dpp_u32(key, ctrl);
+        V vp[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) vp[q] = dpp_v(v[q], ctrl);
+        const bool upper = (lane >> step) & 1;
+        const bool same = key == kp && key != kEmptyKey;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] = (same && !upper) ? (V)(v[q] + vp[q]) : v[q];
+        key = (same && upper) ? kEmptyKey : key;
+    }
+}
+
 template <int MODE>
 struct SweepVals {
     static constexpr int NV = MODE == 2 ? 5 : 4;
@@ -548,9 +584,13 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
                 uint32_t c;
                 int ijk[3];
                 double dr, dtau[NB], tin[NB];
-                if (march_step<NB>(g, a.q, r, m, tau, &stuck, c, ijk, dr, dtau, tin)) {
-                    ++nseg;
-                    if (MODE) {
+                const bool seg = march_step<NB>(g, a.q, r, m, tau, &stuck, c, ijk, dr, dtau, tin);
+                if (seg) ++nseg;
+                if (MODE) {
+                    V v[NV];
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) v[q] = (V)0;
+                    if (seg) {
 #pragma clang fp contract(fast)
                         const float drf = (float)dr;
                         float dLs = 0.0f, j0 = 0.0f, j1 = 0.0f;
@@ -564,14 +604,15 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
                             if (b == 0) j0 = Lin * drf * ph;
                             else j1 = Lin * drf * ph;
                         }
-                        V v[NV];
                         v[0] = quant(j0);
                         v[1] = quant(nxf * dLs);
                         v[2] = quant(nyf * dLs);
                         v[3] = quant(nzf * dLs);
                         if (NV > 4) v[4 % NV] = quant(j1);
-                        pend = dep.deposit(c, ijk, v, pk, pv);
                     }
+                    uint32_t key = seg ? c : kEmptyKey;
+                    quad_combine<NV>(lane, key, v);
+                    if (key != kEmptyKey) pend = dep.deposit(key, ijk, v, pk, pv);
                 }
             }
             if (MODE) {
@@ -965,7 +1006,9 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
                 int ijk[3];
                 double dr, dtau[NB], tin[NB];
                 const float2 qc = m.q;
-                if (march_step<NB>(g, a.q, r, m, tau, &stuck, c, ijk, dr, dtau, tin)) {
+                const bool seg = march_step<NB>(g, a.q, r, m, tau, &stuck, c, ijk, dr, dtau, tin);
+                V v[2] = {(V)0, (V)0};
+                if (seg) {
                     const float4 wv = a.wv[c];
                     const double xv = (double)qc.y, nv = (double)qc.x;
                     const double wa = (double)wv.x * sH * xv * nv;
@@ -996,9 +1039,12 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
                     double gn = dkap[0] * (xv * sH + sd) + wj * xv;
                     if (NB > 1) gn += dkap[NB - 1] * sd;
                     const double gx = dkap[0] * nv * sH + wj * nv;
-                    V v[2] = {quant(gn), quant(gx)};
-                    pend = dep.deposit(c, ijk, v, pk, pv);
+                    v[0] = quant(gn);
+                    v[1] = quant(gx);
                 }
+                // (no quad pre-combine here: the adjoint is bound by its FP64
+                // arithmetic, not by LDS, and the lane moves cost more than they save)
+                if (seg) pend = dep.deposit(c, ijk, v, pk, pv);
             }
             dep.stage(pend, pk, pv);
             dep.flush(acc, lane, (uint32_t)(Dep::CAP - kWave));
