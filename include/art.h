@@ -49,6 +49,7 @@ extern "C" {
 #define ART_ERR_SOURCE_OUTSIDE (-5)   /* device: a source position lies outside the domain */
 #define ART_ERR_DESTROY_COUNT (-6)    /* device: ended rays do not add up to N_src*12*4^level_max */
 #define ART_ERR_NO_FORWARD (-7)       /* adjoint requested on a context built without adjoint support */
+#define ART_ERR_BAD_FIELD (-8)        /* device: a cell has n_H < 0 or not finite, or x_n outside [0, 1] */
 
 #define ART_DEPOSIT_ATOMIC 0          /* FP32 hardware atomics (fast, order-dependent rounding) */
 #define ART_DEPOSIT_DETERMINISTIC 1   /* 64-bit fixed-point integer sums: bitwise reproducible */

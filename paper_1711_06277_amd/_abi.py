@@ -20,6 +20,7 @@ ART_ERR_QUEUE_OVERFLOW = -4
 ART_ERR_SOURCE_OUTSIDE = -5
 ART_ERR_DESTROY_COUNT = -6
 ART_ERR_NO_FORWARD = -7
+ART_ERR_BAD_FIELD = -8
 ART_DEPOSIT_ATOMIC = 0
 ART_DEPOSIT_DETERMINISTIC = 1
 ART_MAX_LEVELS = 16

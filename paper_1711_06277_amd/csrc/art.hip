@@ -161,10 +161,18 @@ __global__ void k_fill_f64(double* p, uint64_t n) {
 // Interleave (n_H, x_n) so that the sweep gathers one 8-byte word per segment.
 // transparent (optional): cells of sink control volumes, where radiation does not
 // interact with the gas (no gas as far as the sweep is concerned).
-__global__ void k_pack(uint64_t N, const float* nH, const float* xn, const uint8_t* transparent, float2* q) {
+// The fields are also checked here (the pass reads every cell anyway): a cell with
+// n_H < 0 or not finite, or x_n outside [0, 1], sets kStBadField.
+__global__ void k_pack(uint64_t N, const float* nH, const float* xn, const uint8_t* transparent, float2* q,
+                       Counters* ct) {
+    bool bad = false;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        q[i] = make_float2((transparent && transparent[i]) ? 0.0f : nH[i], xn[i]);
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const float n = nH[i], x = xn[i];
+        bad = bad || !(n >= 0.0f && n <= 3.4e38f) || !(x >= 0.0f && x <= 1.0f);
+        q[i] = make_float2((transparent && transparent[i]) ? 0.0f : n, x);
+    }
+    if (__ballot(bad) && lane_id() == 0) atomicOr(&ct->c.status, (uint32_t)kStBadField);
 }
 
 // The adjoint's per-cell weights in one 16-byte gather: (w, v_x, v_y, v_z).
@@ -1486,7 +1494,7 @@ int begin_call(art_ctx* c, const float* lum, int n_src, const float* nH, const f
     hipLaunchKernelGGL(k_begin_call, dim3(1), dim3(256), 0, c->stream, c->ct, lum, n_src * c->p.n_bins);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_pack, dim3(fill_blocks(c->N)), dim3(256), 0, c->stream, c->N, nH, xn, c->transparent,
-                       c->q);
+                       c->q, c->ct);
     HIP_TRY(hipGetLastError());
     return ART_OK;
 }
@@ -1505,6 +1513,7 @@ const char* art_strerror(int code) {
         case ART_ERR_SOURCE_OUTSIDE: return "a source lies outside the domain";
         case ART_ERR_DESTROY_COUNT: return "destroy counter does not match N_src*12*4^level_max";
         case ART_ERR_NO_FORWARD: return "context was created without adjoint support";
+        case ART_ERR_BAD_FIELD: return "a cell has n_H < 0 or not finite, or x_n outside [0, 1]";
         default: return "unknown error";
     }
 }
@@ -1705,7 +1714,8 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
         if ((rc = zero(c, c->gk, 2 * N))) return rc;
     }
     // the walk reads the packed fields; pack them again in case the tree is reused
-    hipLaunchKernelGGL(k_pack, dim3(fill_blocks(N)), dim3(256), 0, c->stream, N, n_H, x_n, c->transparent, c->q);
+    hipLaunchKernelGGL(k_pack, dim3(fill_blocks(N)), dim3(256), 0, c->stream, N, n_H, x_n, c->transparent, c->q,
+                       c->ct);
     hipLaunchKernelGGL(k_pack_wv, dim3(fill_blocks(N)), dim3(256), 0, c->stream, N, g_rate, g_force, c->wv);
     HIP_TRY(hipGetLastError());
     AdjArgs aa;
@@ -1757,6 +1767,7 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
 static int status_code(const Counters& h, uint64_t expected) {
     if (h.c.status & kStOverflow) return ART_ERR_QUEUE_OVERFLOW;
     if (h.c.status & kStOutside) return ART_ERR_SOURCE_OUTSIDE;
+    if (h.c.status & kStBadField) return ART_ERR_BAD_FIELD;
     if (h.c.status & kStStuck) return ART_ERR_INVALID_ARG;
     if (h.c.destroy != expected) return ART_ERR_DESTROY_COUNT;
     return ART_OK;

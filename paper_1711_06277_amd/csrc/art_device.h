@@ -27,6 +27,7 @@ enum Status : uint32_t {
     kStOverflow = 1u,
     kStOutside = 2u,
     kStStuck = 4u,
+    kStBadField = 8u,  // a cell with n_H < 0 or non-finite, or x_n outside [0, 1]
 };
 
 // Per-call constants of the sweep, passed by value to every kernel.

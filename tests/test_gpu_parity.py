@@ -164,3 +164,39 @@ def test_rotated_directions(oracle):
     tree_equal(st, ref)
     compare_cells("rate", rate, ref.rate, float(wl.src_lum.sum()))
 
+
+
+@pytest.mark.parametrize("bad", ["nan_density", "negative_density", "fraction_above_one"])
+def test_bad_fields_are_reported(bad):
+    """Fields outside the method's domain (n_H < 0 or not finite, x_n outside [0, 1])
+    are flagged on the device and reported as ART_ERR_BAD_FIELD; the sweep still
+    ends (no ray loops on a non-finite optical depth)."""
+    from paper_1711_06277_amd._abi import ART_ERR_BAD_FIELD, ArtError
+    wl = small_lognormal(n_src=2)
+    wl.n_H = wl.n_H.copy()
+    wl.x_n = wl.x_n.copy()
+    c = wl.n_cells // 2
+    if bad == "nan_density":
+        wl.n_H[c] = np.nan
+    elif bad == "negative_density":
+        wl.n_H[c] = -1.0
+    else:
+        wl.x_n[c] = 1.5
+    with pytest.raises(ArtError) as e:
+        run_gpu(wl)
+    assert e.value.code == ART_ERR_BAD_FIELD
+
+
+def test_atomic_mode_matches_fixed_point_mode():
+    """The two deposit modes give the same fields to 1e-4 relative (the FP32 atomics
+    add in a different order on every run; the fixed-point sums do not)."""
+    wl = small_lognormal(seed=44)
+    (ra, fa, Ja), st_a = run_gpu(wl, deterministic=False)
+    (rd, fd, Jd), st_d = run_gpu(wl, deterministic=True)
+    assert st_a.status == st_d.status == 0
+    L = float(wl.src_lum.astype(np.float64).sum())
+    compare_cells("rate", ra, rd.astype(np.float64), L)
+    for b in range(wl.n_bins):
+        compare_cells(f"J{b}", Ja[b], Jd[b].astype(np.float64), L)
+    kj = sum(k * j.astype(np.float64) for k, j in zip(kappas(wl), Jd))
+    compare_force(fa, fd.astype(np.float64), L, kj)

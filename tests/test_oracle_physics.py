@@ -426,3 +426,31 @@ def test_tangent_vs_central_differences(oracle):
     fd_force = (out[0].force - out[1].force) / (2 * h)
     assert np.allclose(drate, fd_rate, rtol=1e-5, atol=1e-7 * np.abs(drate).max())
     assert np.allclose(dforce, fd_force, rtol=1e-5, atol=1e-7 * np.abs(dforce).max())
+
+
+def test_momentum_bookkeeping(oracle):
+    """Sec. 2.1: the force deposited in the cells adds up to the momentum the rays
+    lose, sum over rays of n_ray (L_nom e^{-tau_start} - L_nom e^{-tau_end}); the
+    ray sum is taken by walking the tree by hand in a uniform medium."""
+    n, xs, kappa = 20, np.array([9.7, 10.2, 10.6]), 0.25
+    wl = I.uniform_workload(n, xs, lum=1.0, s_H=kappa, s_d=0.0, n_bins=1, tau_term=60.0)
+    res = oracle.trace_workload(wl)
+    lost = np.zeros(3)
+    stack = [(2, p, 0.0) for p in range(12 * 16)]
+    while stack:
+        lev, pix, tau = stack.pop()
+        v = oracle.pix2vec_nest(lev, pix)
+        with np.errstate(divide="ignore"):
+            t = np.where(v > 0, (n - xs) / v, np.where(v < 0, -xs / v, np.inf))
+        d_exit = t.min()
+        r_a = oracle.r_max(4.0, lev - 1) if lev > 2 else 0.0
+        r_s = oracle.r_max(4.0, lev) if lev < 13 else np.inf
+        if r_a >= d_exit:
+            continue
+        cells, dr = oracle.ray_segments((n, n, n), xs, v, r_a, min(r_s, d_exit))
+        tau_end = tau + kappa * float(dr.sum())
+        lost += v * (math.exp(-tau) - math.exp(-tau_end)) / (12 * 4 ** lev)
+        if r_s < d_exit:
+            stack += [(lev + 1, 4 * pix + k, tau_end) for k in range(4)]
+    assert np.allclose(res.force.sum(axis=1), lost, rtol=1e-10, atol=1e-14)
+    assert np.linalg.norm(lost) > 1e-4  # the off-centre source makes the sum nonzero
