@@ -150,6 +150,12 @@ int art_autotune(art_ctx *ctx, const float *n_H, const float *x_n, const double 
                  const float *src_lum, int n_src, float *rate, float *force,
                  int *best_block_size, int *best_blocks_per_cu, float *best_ms);
 
+/* Set the launch shape of the sweep kernels (as art_options.block_size and
+ * blocks_per_cu; 0 selects the default), e.g. a shape art_autotune found earlier
+ * for the same grid and source count.  ART_ERR_INVALID_ARG for a shape outside the
+ * ranges art_create accepts. */
+int art_set_launch(art_ctx *ctx, int block_size, int blocks_per_cu);
+
 /* Average duration in ms of the per-level sweep launches of the last forward
  * call (HIP events on the context's stream; enable with art_set_timing). */
 int art_set_timing(art_ctx *ctx, int enable);

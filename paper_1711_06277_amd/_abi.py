@@ -28,7 +28,7 @@ ART_MAX_BINS = 2
 
 # every symbol declared in include/art.h
 EXPORTED = ("art_create", "art_set_stream", "art_trace", "art_trace_adjoint", "art_sync",
-            "art_get_stats", "art_autotune", "art_set_timing", "art_get_timing",
+            "art_get_stats", "art_autotune", "art_set_launch", "art_set_timing", "art_get_timing",
             "art_set_transparent", "art_set_rotation", "art_random_rotation", "art_get_rotation",
             "art_ion_substep", "art_ion_subcycle", "art_destroy", "art_strerror")
 
@@ -85,6 +85,7 @@ def lib() -> C.CDLL:
         L.art_get_stats.argtypes = [vp, C.POINTER(art_stats), C.c_int, vp, vp, vp, vp, vp, vp, vp]
         L.art_autotune.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, C.POINTER(C.c_int),
                                    C.POINTER(C.c_int), C.POINTER(C.c_float)]
+        L.art_set_launch.argtypes = [vp, C.c_int, C.c_int]
         L.art_set_timing.argtypes = [vp, C.c_int]
         L.art_get_timing.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_int),
                                      C.POINTER(C.c_float)]
@@ -158,6 +159,10 @@ def art_autotune(ctx, n_H, x_n, src_pos, src_lum, n_src, rate, force):
     check(lib().art_autotune(C.c_void_p(ctx), n_H, x_n, src_pos, src_lum, int(n_src), rate, force,
                              C.byref(bb), C.byref(bp), C.byref(ms)), "art_autotune")
     return bb.value, bp.value, ms.value
+
+
+def art_set_launch(ctx, block_size: int, blocks_per_cu: int):
+    check(lib().art_set_launch(C.c_void_p(ctx), int(block_size), int(blocks_per_cu)), "art_set_launch")
 
 
 def art_set_timing(ctx, enable: bool):

@@ -7,7 +7,9 @@ built library or a GPU these calls raise.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -255,7 +257,32 @@ class ArtTracer:
             src_escaped=esc[:n, : self.n_bins], src_residual=res[:n, : self.n_bins],
             src_segments=seg[:n].astype(np.int64))
 
-    def autotune(self, n_H, x_n, src_pos, src_lum):
+    def autotune_key(self, n_src: int) -> str:
+        """Cache key of a launch shape: GPU name, grid, sources, bins, deposit mode, levels, m_ray."""
+        p = self.params
+        return "|".join([torch.cuda.get_device_name(self.device), "x".join(map(str, self.shape)),
+                         f"src{int(n_src)}", f"bins{self.n_bins}", f"mode{p.deposit_mode}",
+                         f"l{p.level0}-{p.level_max}", f"m{p.phi_c:g}"])
+
+    def autotune(self, n_H, x_n, src_pos, src_lum, *, cache=None):
+        """Time the built-in launch shapes on these inputs and keep the fastest; returns
+        (block_size, blocks_per_cu, ms).  With ``cache`` (a JSON file path, or True for
+        $ART_AUTOTUNE_CACHE or ~/.cache/art_mi355x/autotune.json) a shape found before
+        for the same key is applied without timing, and new results are stored."""
+        path = autotune_cache_path(cache)
+        n_src = int(np.asarray(src_pos).reshape(-1, 3).shape[0]) if not isinstance(src_pos, torch.Tensor) \
+            else int(src_pos.reshape(-1, 3).shape[0])
+        if path is not None:
+            hit = load_autotune_cache(path).get(self.autotune_key(n_src))
+            if hit is not None:
+                A.art_set_launch(self._ctx, hit[0], hit[1])
+                return int(hit[0]), int(hit[1]), float(hit[2])
+        result = self._autotune(n_H, x_n, src_pos, src_lum)
+        if path is not None:
+            store_autotune_cache(path, self.autotune_key(n_src), result)
+        return result
+
+    def _autotune(self, n_H, x_n, src_pos, src_lum):
         d = self.device
         n_H = _dev(n_H, torch.float32, d).reshape(-1)
         x_n = _dev(x_n, torch.float32, d).reshape(-1)
@@ -274,6 +301,36 @@ class ArtTracer:
     def timing(self):
         """(sum of sweep-kernel durations in ms, number of sweep launches, whole call ms)."""
         return A.art_get_timing(self._ctx)
+
+
+def autotune_cache_path(cache):
+    """None (no cache), an explicit path, or for True the default location."""
+    if cache is None or cache is False:
+        return None
+    if cache is True:
+        return os.environ.get("ART_AUTOTUNE_CACHE",
+                              os.path.join(os.path.expanduser("~"), ".cache", "art_mi355x", "autotune.json"))
+    return str(cache)
+
+
+def load_autotune_cache(path) -> dict:
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def store_autotune_cache(path, key, result) -> None:
+    """Add one (block_size, blocks_per_cu, ms) entry, replacing the file atomically."""
+    data = load_autotune_cache(path)
+    data[key] = [int(result[0]), int(result[1]), float(result[2])]
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
 
 
 class ArtTrace(torch.autograd.Function):

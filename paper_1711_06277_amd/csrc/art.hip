@@ -1891,6 +1891,17 @@ int art_autotune(art_ctx* c, const float* n_H, const float* x_n, const double* s
     return art_sync(c);
 }
 
+int art_set_launch(art_ctx* c, int block_size, int blocks_per_cu) {
+    if (!c) return ART_ERR_INVALID_ARG;
+    if (block_size == 0) block_size = 64;
+    if (blocks_per_cu == 0) blocks_per_cu = 16;
+    if (block_size < 64 || block_size > 256 || (block_size % 64) || blocks_per_cu < 1 || blocks_per_cu > 64)
+        return ART_ERR_INVALID_ARG;
+    c->o.block_size = block_size;
+    c->o.blocks_per_cu = blocks_per_cu;
+    return ART_OK;
+}
+
 int art_set_transparent(art_ctx* c, const uint8_t* transparent) {
     if (!c) return ART_ERR_INVALID_ARG;
     c->transparent = transparent;
