@@ -78,6 +78,12 @@ struct Pool {
     uint32_t* child;  // pool index of the first of the four children (or kNoChild)
     double* G;        // [cap][2]: adjoint, loss contributed downstream of the start
     double* tend;     // [cap][2]: optical depth where a splitting ray split; -1 if it did not
+    // adjoint tape (NULL without adjoint support): the cell of each ray's last
+    // segment (kNoChild if it has none), that segment's upper end, and the
+    // optical depth at the ray's end
+    uint32_t* last;
+    double* rlast;
+    double* taulast;  // [cap][2]
     uint32_t* tsum;   // children per tile of kSplitTile parents, then their exclusive prefix
     uint64_t cap;
 };
@@ -584,7 +590,9 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
         }
         // converged march: one segment per lane per iteration
         const float nxf = (float)r.n[0], nyf = (float)r.n[1], nzf = (float)r.n[2];
-        while (__ballot(m.alive)) {
+        // The loop body twice per iteration: the march state then alternates
+        // between two register sets instead of being copied back every step.
+        auto step = [&]() __attribute__((always_inline)) {
             bool pend = false;
             uint32_t pk = 0;
             V pv[NV];
@@ -627,8 +635,19 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
                 dep.stage(pend, pk, pv);
                 dep.flush(acc, lane, (uint32_t)(Dep::CAP - kWave));
             }
+        };
+        while (__ballot(m.alive)) {
+            step();
+            if (__ballot(m.alive) == 0ull) break;
+            step();
         }
         const int end = m.end;
+        if (active && a.pool.last) {
+            a.pool.last[slot] = nseg ? m.c : kNoChild;
+            a.pool.rlast[slot] = m.rr;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) a.pool.taulast[2 * slot + b] = b < NB ? tau[b] : 0.0;
+        }
         if (active && end != kSplit) {
 #pragma unroll
             for (int b = 0; b < NB; ++b)
@@ -880,24 +899,21 @@ __global__ void k_finalize(uint64_t N, const float* nH, const float* xn, const u
 // --------------------------------------------------------------------------
 
 
-// For every ray of the level: pass 1 recomputes its segments and sums its own
-// per-bin loss contributions T_b; G_b(start) = T_b + sum of the children's
-// G_b(start) is stored for the parent level.  Pass 2 walks the same segments
-// again and deposits dL/dkappa_b of each cell:
+// For every ray of the level, its segments are walked once, backwards (from the
+// tape's last cell to the ray's start), depositing dL/dkappa_b of each crossed
+// cell:
 //   [b = ionizing] a L_in dr^2 phi'(dtau) + beta L_in dr e^{-dtau} - dr G_b(after the segment)
 // with a = w s_H x_n n_H (the rate weight) and beta = v . n (the force weight):
 // every downstream contribution is proportional to e^{-tau}, so its derivative
-// with respect to this segment's opacity is -dr times its value.
-//
-// The walk is the forward sweep's (march_step over the same packed fields), so
-// the segments and the tree are the forward's.  The transmission e^{-tau_b}
-// is carried along the ray as a product of the segments' e^{-dtau}, identical
-// in both passes, so P_b (pass 2's running sum of the own terms) reaches T_b
-// exactly at the ray's end.  The gradient of a cell is a sum of terms of both
-// signs (the explicit absorption terms against -dr G of everything
-// downstream), so the per-segment arithmetic is FP64 and the two values per
-// cell go through the same LDS cache as the forward deposits, as FP64 or as
-// 64-bit fixed point.
+// with respect to this segment's opacity is -dr times its value.  Walking
+// backwards, G_b(after) is the children's G_b(start) plus the ray's own loss
+// terms of the segments already walked; at the start it is G_b(start), stored
+// for the parent level.  L_in = L_nom e^{-tau_in} comes from the end's optical
+// depth (tape) by removing each segment's dtau.  The segments are those of the
+// forward walk (same expressions), and the tree is the forward's.  The gradient
+// of a cell is a sum of terms of both signs, so the per-segment arithmetic is
+// FP64 and the two values per cell go through the same LDS cache as the
+// forward deposits, as FP64 or as 64-bit fixed point.
 template <int NB, bool DET>
 __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
     using V = typename std::conditional<DET, unsigned long long, double>::type;
@@ -928,27 +944,30 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
         if (__ballot(active) == 0ull) break;
         const uint64_t slot = off + (active ? li : 0u);
 
-        uint32_t src = 0, pix = 0;
-        double tau0[NB], E0[NB], lnom[NB], Gend[NB], T[NB];
+        uint32_t src = 0, pix = 0, last = kNoChild;
+        double tau[NB], E[NB], lnom[NB], Gend[NB], A[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            tau0[b] = 0.0;
-            E0[b] = 1.0;
+            tau[b] = 0.0;
+            E[b] = 1.0;
             lnom[b] = 0.0;
             Gend[b] = 0.0;
-            T[b] = 0.0;
+            A[b] = 0.0;
         }
         bool run = false, stuck = false;
         Ray r;
+        BackState m;
+        m.alive = false;
         if (active) {
             src = a.pool.src[slot];
             pix = a.pool.pix[slot];
+            last = a.pool.last[slot];
             const bool ok = src < a.n_src;  // always true for a written slot
             if (!ok) src = 0;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                tau0[b] = a.pool.tau[2 * slot + b];
-                E0[b] = exp(-tau0[b]);
+                tau[b] = a.pool.taulast[2 * slot + b];
+                E[b] = exp(-tau[b]);
                 lnom[b] = (double)a.src_lum[(uint64_t)src * NB + b] * inv_nray;
             }
             const uint32_t ch = a.pool.child[slot];
@@ -958,53 +977,11 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
                     for (int b = 0; b < NB; ++b) Gend[b] += a.pool.G[2 * ((uint64_t)ch + k) + b];
             }
             ray_setup(g, a.src_pos, src, level, pix, r);
-            run = ok && source_inside(g, r.xs) && !r.starts_outside;
+            run = ok && last != kNoChild && source_inside(g, r.xs) && !r.starts_outside;
+            if (run) back_begin(g, a.q, r, last, a.pool.rlast[slot], m);
         }
         const double nx = r.n[0], ny = r.n[1], nz = r.n[2];
 
-        // ---- pass 1: T_b, the ray's own loss contributions ----
-        MarchState m;
-        m.alive = false;
-        m.end = kExit;
-        double tau[NB], E[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            tau[b] = tau0[b];
-            E[b] = E0[b];
-        }
-        if (run) march_begin(g, a.q, r, m);
-        while (__ballot(m.alive)) {
-            uint32_t c;
-            int ijk[3];
-            double dr, dtau[NB], tin[NB];
-            const float2 qc = m.q;
-            if (march_step<NB>(g, a.q, r, m, tau, &stuck, c, ijk, dr, dtau, tin)) {
-                const float4 wv = a.wv[c];
-                const double wa = (double)wv.x * sH * (double)qc.y * (double)qc.x;
-                const double beta = (double)wv.y * nx + (double)wv.z * ny + (double)wv.w * nz;
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const double x = dtau[b];
-                    const double Lin = lnom[b] * E[b];
-                    const double om = -expm1(-x);
-                    double own = beta * Lin * om;
-                    if (b == 0) own += wa * Lin * dr * absorb_phi(x, om);
-                    T[b] += own;
-                    E[b] *= 1.0 - om;
-                }
-            }
-        }
-
-        // ---- pass 2: dL/dkappa_b of every crossed cell ----
-        m.alive = false;
-        double P[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            tau[b] = tau0[b];
-            E[b] = E0[b];
-            P[b] = 0.0;
-        }
-        if (run) march_begin(g, a.q, r, m);
         while (__ballot(m.alive)) {
             bool pend = false;
             uint32_t pk = 0;
@@ -1012,9 +989,9 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
             {
                 uint32_t c;
                 int ijk[3];
-                double dr, dtau[NB], tin[NB];
+                double dr, dtau[NB];
                 const float2 qc = m.q;
-                const bool seg = march_step<NB>(g, a.q, r, m, tau, &stuck, c, ijk, dr, dtau, tin);
+                const bool seg = back_step<NB>(g, a.q, r, m, &stuck, c, ijk, dr, dtau);
                 V v[2] = {(V)0, (V)0};
                 if (seg) {
                     const float4 wv = a.wv[c];
@@ -1025,9 +1002,15 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         const double x = dtau[b];
-                        const double Lin = lnom[b] * E[b];
                         const double om = -expm1(-x);
                         const double e = 1.0 - om;
+                        // transmission at the segment's entry: E(out) / e^{-dtau}, or
+                        // directly where either underflows
+                        tau[b] -= x;
+                        double Ein = E[b] / e;
+                        if (!(E[b] > 1e-290 && e > 1e-290)) Ein = exp(-tau[b]);
+                        E[b] = Ein;
+                        const double Lin = lnom[b] * Ein;
                         double own = beta * Lin * om;
                         double dk = beta * Lin * dr * e;
                         if (b == 0) {
@@ -1036,10 +1019,8 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
                             own += wa * j0;
                             dk += wa * Lin * dr * dr * absorb_dphi(x, e, om);
                         }
-                        P[b] += own;
-                        const double after = (T[b] - P[b]) + Gend[b];
-                        dkap[b] = dk - dr * after;
-                        E[b] *= e;
+                        dkap[b] = dk - dr * (A[b] + Gend[b]);
+                        A[b] += own;
                     }
                     // chain rule through kappa_0 = n_H (x_n s_H + s_d), kappa_1 = n_H s_d,
                     // plus the explicit n_H x_n factor of rate = s_H x_n n_H J_0
@@ -1050,8 +1031,6 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
                     v[0] = quant(gn);
                     v[1] = quant(gx);
                 }
-                // (no quad pre-combine here: the adjoint is bound by its FP64
-                // arithmetic, not by LDS, and the lane moves cost more than they save)
                 if (seg) pend = dep.deposit(c, ijk, v, pk, pv);
             }
             dep.stage(pend, pk, pv);
@@ -1062,7 +1041,7 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
         }
         if (active) {
 #pragma unroll
-            for (int b = 0; b < NB; ++b) a.pool.G[2 * slot + b] = T[b] + Gend[b];
+            for (int b = 0; b < NB; ++b) a.pool.G[2 * slot + b] = A[b] + Gend[b];
         }
     }
     dep.drain(acc, lane);
@@ -1342,6 +1321,9 @@ void free_all(art_ctx* c) {
     (void)hipFree(c->pool.tau);
     (void)hipFree(c->pool.child);
     (void)hipFree(c->pool.G);
+    (void)hipFree(c->pool.last);
+    (void)hipFree(c->pool.rlast);
+    (void)hipFree(c->pool.taulast);
     (void)hipFree(c->pool.tend);
     (void)hipFree(c->pool.tsum);
     (void)hipFree(c->ct);
@@ -1568,7 +1550,7 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
     // ray pool
     c->per_src_bound = rays_bound_per_source(nx, ny, nz, *params);
     c->deepest = deepest_level(nx, ny, nz, *params);
-    const uint64_t bytes_per_ray = 4 + 4 + 16 + 16 + (o.enable_adjoint ? 4 + 16 : 0);
+    const uint64_t bytes_per_ray = 4 + 4 + 16 + 16 + (o.enable_adjoint ? 4 + 16 + 4 + 8 + 16 : 0);
     uint64_t cap = (uint64_t)o.pool_rays;
     if (cap == 0) {
         size_t free_b = 0, total_b = 0;
@@ -1601,7 +1583,8 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
               dmalloc(&c->st.residual, ms * 2) && dmalloc(&c->st.segments, ms) && dmalloc(&c->fscratch, 64) &&
               dmalloc(&c->ion, 4) && dmalloc(&c->rot, 9);
     if (ok && o.enable_adjoint)
-        ok = dmalloc(&c->pool.child, cap) && dmalloc(&c->pool.G, 2 * cap);
+        ok = dmalloc(&c->pool.child, cap) && dmalloc(&c->pool.G, 2 * cap) && dmalloc(&c->pool.last, cap) &&
+             dmalloc(&c->pool.rlast, cap) && dmalloc(&c->pool.taulast, 2 * cap);
     if (ok) ok = det ? dmalloc(&c->det, 8 * N) : dmalloc(&c->acc, 8 * N);
     if (ok) ok = dmalloc(&c->q, N);
     if (ok && o.enable_adjoint) ok = det ? dmalloc(&c->gdet, 2 * N) : dmalloc(&c->gk, 2 * N);

@@ -266,6 +266,108 @@ __device__ __forceinline__ bool march_step(const Geo& g, const float2* __restric
     return seg;
 }
 
+// The same segments walked backwards, from the last one to the first.  The
+// entry face of a cell on an axis is the exit face the forward walk computed in
+// the neighbouring cell, by the same expression ((face - x_s) / n_a), so the
+// segment ends, ties (axes stepping together) and zero-length skips are those
+// of march_step, in reverse order.  Starts in the cell of the ray's last segment,
+// whose end is r_hi; ends at the ray's start r_a.  Optical depth is not tracked
+// here (the caller has the forward's end value).
+struct BackState {
+    int cell[3];
+    int start[3];     // the forward walk's first cell (where the backward walk stops)
+    double tprev[3];  // entry-face parameter of the current cell per axis
+    double rhi;       // upper end of the current segment
+    uint32_t c;
+    float2 q;
+    int it, max_steps;
+    bool alive;
+};
+
+__device__ __forceinline__ double entry_face(const Ray& r, int a, int cell) {
+    if (r.n[a] > 0.0) return ((double)cell - r.xs[a]) * r.inv[a];
+    if (r.n[a] < 0.0) return ((double)(cell + 1) - r.xs[a]) * r.inv[a];
+    return -INFINITY;
+}
+
+__device__ inline void back_begin(const Geo& g, const float2* __restrict__ q, const Ray& r, uint32_t last_cell,
+                                  double r_last, BackState& m) {
+    const uint32_t nxy = (uint32_t)g.nx * (uint32_t)g.ny;
+    m.cell[2] = (int)(last_cell / nxy);
+    const uint32_t rem = last_cell - (uint32_t)m.cell[2] * nxy;
+    m.cell[1] = (int)(rem / (uint32_t)g.nx);
+    m.cell[0] = (int)(rem - (uint32_t)m.cell[1] * (uint32_t)g.nx);
+    const int dims[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        m.tprev[a] = entry_face(r, a, m.cell[a]);
+        // the start cell exactly as march_begin finds it
+        const double p = r.xs[a] + r.r_a * r.n[a];
+        int c = (int)floor(p);
+        m.start[a] = c < 0 ? 0 : (c > dims[a] - 1 ? dims[a] - 1 : c);
+    }
+    m.rhi = r_last;
+    m.c = last_cell;
+    m.q = q[last_cell];
+    m.it = 0;
+    m.max_steps = g.nx + g.ny + g.nz + 8;
+    m.alive = true;
+}
+
+// One segment backwards, branch-free like march_step.  Returns true if the lane
+// produced a segment of positive length (c, ijk, dr, dtau describe it).
+template <int NB>
+__device__ __forceinline__ bool back_step(const Geo& g, const float2* __restrict__ q, const Ray& r, BackState& m,
+                                          bool* stuck, uint32_t& c, int (&ijk)[3], double& dr, double (&dtau)[NB]) {
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    const bool alive = m.alive;
+    const bool budget = m.it < m.max_steps;
+    m.it += 1;
+    const double lo0 = fmax(fmax(m.tprev[0], m.tprev[1]), m.tprev[2]);
+    // the ray's first segment: the forward's start cell (whose entry face can lie a
+    // rounding error beyond r_a), or an entry face at or before r_a
+    const bool first = (m.cell[0] == m.start[0] && m.cell[1] == m.start[1] && m.cell[2] == m.start[2]) ||
+                       !(lo0 > r.r_a);
+    const double rlo = first ? r.r_a : lo0;
+    dr = m.rhi - rlo;
+    const bool seg = alive && budget && dr > 0.0;
+    c = m.c;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ijk[a] = m.cell[a];
+    const double dnH = (double)m.q.x;
+    double kap[NB];
+    kap[0] = dnH * ((double)m.q.y * g.s_H + g.s_d);
+    if (NB > 1) kap[NB - 1] = dnH * g.s_d;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) dtau[b] = kap[b] * dr;
+    const bool go = alive && budget && !first;
+    bool moved = false, out = false;
+    int nc[3];
+    bool st[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        st[a] = m.tprev[a] == lo0;
+        nc[a] = m.cell[a] - (r.n[a] > 0.0 ? 1 : -1);
+        moved = moved || st[a];
+        out = out || (st[a] && (nc[a] < 0 || nc[a] >= dims[a]));
+    }
+    const bool adv = go && moved && !out;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool s2 = adv && st[a];
+        m.cell[a] = s2 ? nc[a] : m.cell[a];
+        m.tprev[a] = s2 ? entry_face(r, a, nc[a]) : m.tprev[a];
+    }
+    m.rhi = adv ? lo0 : m.rhi;
+    *stuck = *stuck || (alive && (!budget || (go && (!moved || out))));
+    m.alive = alive && adv;
+    if (adv) {
+        m.c = cell_index(g, m.cell);
+        m.q = q[m.c];
+    }
+    return seg;
+}
+
 // (1 - e^{-x})/x and 1 - e^{-x} in FP32, accurate for small x (series below
 // 0.1, where 1 - e^{-x} would cancel), branch-free.
 __device__ __forceinline__ void absorb_factors(float x, float& phi, float& one_minus_e) {
