@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 # method's 40 B in both modes.
 BYTES_PER_SEGMENT = 40
 BYTES_PER_SEGMENT_FIXED_POINT = 72
-# the adjoint walks every segment twice: both passes gather (n_H, x_n, w, v)
-# (24 B), the second adds dL/dn_H and dL/dx_n to two FP64 cells (2 x 16 B RMW)
-ADJOINT_BYTES_PER_SEGMENT = 80
+# the adjoint walks every segment once (backwards): it gathers (n_H, x_n, w, v)
+# (24 B) and adds dL/dn_H and dL/dx_n to two FP64 cells (2 x 16 B RMW)
+ADJOINT_BYTES_PER_SEGMENT = 56
 
 
 def log(*a):
@@ -276,7 +276,7 @@ def main():
                    "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "frac": adj_gbs / HBM_PEAK_GBS,
                                 "kernel": "k_adjoint (one launch per level, deepest first; "
-                                          "both passes over every segment)",
+                                          "one backward walk over every segment)",
                                 "bytes_per_segment": ADJOINT_BYTES_PER_SEGMENT}}
         log(f"[bench] adjoint: {1e3 * adj_s:.2f} ms per adjoint sweep "
             f"({segments / adj_s:.3e} segments/s), forward with tree "
