@@ -982,7 +982,8 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
         }
         const double nx = r.n[0], ny = r.n[1], nz = r.n[2];
 
-        while (__ballot(m.alive)) {
+        // two steps per iteration, as in the forward sweep
+        auto step = [&]() __attribute__((always_inline)) {
             bool pend = false;
             uint32_t pk = 0;
             V pv[2];
@@ -1035,6 +1036,11 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
             }
             dep.stage(pend, pk, pv);
             dep.flush(acc, lane, (uint32_t)(Dep::CAP - kWave));
+        };
+        while (__ballot(m.alive)) {
+            step();
+            if (__ballot(m.alive) == 0ull) break;
+            step();
         }
         if (__ballot(stuck)) {
             if (lane == 0) atomicOr(&ct->c.status, (uint32_t)kStStuck);
