@@ -314,10 +314,11 @@ __global__ void k_seed(Pool pool, Counters* ct, int level0, int src0, int n_wave
 constexpr uint32_t kEmptyKey = 0xffffffffu;
 #define ART_LDS __attribute__((address_space(3)))
 
-template <int NV, class V_>
+template <int NV, class V_, int S_>
 struct Deposit {
     using V = V_;  // float, double, or unsigned 64-bit fixed point (two's complement sums)
-    static constexpr int S = 256;          // cache slots
+    static constexpr int S = S_;           // cache slots: 128 or 256
+    static_assert(S_ == 128 || S_ == 256, "the slot map is an 8 x 8 x (S/64) tile");
     static constexpr int CAP = 128;        // staging capacity (>= 64 + flush threshold)
     // Staging row stride: the flush reads rows f = 0..3 at one column each; a
     // stride of 144 words puts those rows 16 (FP32) or 32 (64-bit) banks apart.
@@ -340,13 +341,13 @@ struct Deposit {
         return Deposit{k, v, k + S, sv, 0u};
     }
 
-    // The cell's position in an 8 x 8 x 4 tile, with the tile's upper bits folded
-    // into the lower ones (a bijection): the lanes of a wavefront cross a patch of
-    // neighbouring cells, and without the fold cells that differ only in k (or in
-    // the high bit of j) would share LDS banks.
+    // The cell's position in an 8 x 8 x (S/64) tile, with the tile's upper bits
+    // folded into the lower ones (a bijection): the lanes of a wavefront cross a
+    // patch of neighbouring cells, and without the fold cells that differ only in k
+    // (or in the high bit of j) would share LDS banks.
     __device__ static inline uint32_t slot(const int (&ijk)[3]) {
-        const uint32_t h = (uint32_t)((ijk[0] & 7) | ((ijk[1] & 7) << 3) | ((ijk[2] & 3) << 6));
-        return h ^ ((h >> 4) & 0xfu);
+        const uint32_t h = (uint32_t)((ijk[0] & 7) | ((ijk[1] & 7) << 3) | ((ijk[2] & (S / 64 - 1)) << 6));
+        return h ^ ((h >> 4) & (uint32_t)(S / 16 - 1));
     }
     __device__ static inline void lds_add(ART_LDS float* p, float x) {
         __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -482,27 +483,25 @@ struct Deposit {
 // adds the upper lane's values and the upper lane drops its deposit.  Same-address
 // LDS atomics serialise, so this removes most of the LDS cache's address and bank
 // conflicts for a few VALU instructions.  Converged code (every lane present).
+// The values are FP32 (before any fixed-point conversion): one lane move each.
 __device__ __forceinline__ uint32_t dpp_u32(uint32_t x, int ctrl) {
     return ctrl == 0xB1 ? (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false)
                         : (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);
 }
-__device__ __forceinline__ unsigned long long dpp_v(unsigned long long x, int ctrl) {
-    return ((unsigned long long)dpp_u32((uint32_t)(x >> 32), ctrl) << 32) | dpp_u32((uint32_t)x, ctrl);
-}
 __device__ __forceinline__ float dpp_v(float x, int ctrl) { return __uint_as_float(dpp_u32(__float_as_uint(x), ctrl)); }
-template <int NV, class V>
-__device__ __forceinline__ void quad_combine(int lane, uint32_t& key, V (&v)[NV]) {
+template <int NV>
+__device__ __forceinline__ void quad_combine(int lane, uint32_t& key, float (&v)[NV]) {
 #pragma unroll
     for (int step = 0; step < 2; ++step) {
         const int ctrl = step == 0 ? 0xB1 : 0x4E;
         const uint32_t kp = dpp_u32(key, ctrl);
-        V vp[NV];
+        float vp[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) vp[q] = dpp_v(v[q], ctrl);
         const bool upper = (lane >> step) & 1;
         const bool same = key == kp && key != kEmptyKey;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) v[q] = (same && !upper) ? (V)(v[q] + vp[q]) : v[q];
+        for (int q = 0; q < NV; ++q) v[q] = (same && !upper) ? v[q] + vp[q] : v[q];
         key = (same && upper) ? kEmptyKey : key;
     }
 }
@@ -511,11 +510,17 @@ template <int MODE>
 struct SweepVals {
     static constexpr int NV = MODE == 2 ? 5 : 4;
 };
+// Forward deposits: a 128-slot cache keeps a wavefront's LDS at 9.5 KB (64-bit
+// values), so 16 wavefronts fit a CU; the adjoint keeps 256 slots.
+constexpr int kSweepSlots = 128;
+constexpr int kAdjointSlots = 256;
 
 template <int NB, bool DET, int MODE>
-__global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
+// Four wavefronts per SIMD (at most 128 VGPRs): the march is latency bound, and
+// the few registers this spills are outside the loop.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_sweep(SweepArgs a, int level) {
     constexpr int NV = SweepVals<MODE>::NV;
-    using Dep = Deposit<NV, typename std::conditional<DET, unsigned long long, float>::type>;
+    using Dep = Deposit<NV, typename std::conditional<DET, unsigned long long, float>::type, kSweepSlots>;
     using V = typename Dep::V;
     // Dynamic LDS: Dep::kBytes per wavefront of the workgroup (none in MODE 0)
     extern __shared__ __align__(16) unsigned char sweep_lds[];
@@ -603,9 +608,9 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
                 const bool seg = march_step<NB>(g, a.q, r, m, tau, &stuck, c, ijk, dr, dtau, tin);
                 if (seg) ++nseg;
                 if (MODE) {
-                    V v[NV];
+                    float v[NV];
 #pragma unroll
-                    for (int q = 0; q < NV; ++q) v[q] = (V)0;
+                    for (int q = 0; q < NV; ++q) v[q] = 0.0f;
                     if (seg) {
 #pragma clang fp contract(fast)
                         const float drf = (float)dr;
@@ -620,15 +625,22 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int level) {
                             if (b == 0) j0 = Lin * drf * ph;
                             else j1 = Lin * drf * ph;
                         }
-                        v[0] = quant(j0);
-                        v[1] = quant(nxf * dLs);
-                        v[2] = quant(nyf * dLs);
-                        v[3] = quant(nzf * dLs);
-                        if (NV > 4) v[4 % NV] = quant(j1);
+                        v[0] = j0;
+                        v[1] = nxf * dLs;
+                        v[2] = nyf * dLs;
+                        v[3] = nzf * dLs;
+                        if (NV > 4) v[4 % NV] = j1;
                     }
+                    // combined in FP32, then quantised: the pairs are fixed by the
+                    // lane order, so fixed-point results stay reproducible
                     uint32_t key = seg ? c : kEmptyKey;
                     quad_combine<NV>(lane, key, v);
-                    if (key != kEmptyKey) pend = dep.deposit(key, ijk, v, pk, pv);
+                    if (key != kEmptyKey) {
+                        V vq[NV];
+#pragma unroll
+                        for (int q = 0; q < NV; ++q) vq[q] = quant(v[q]);
+                        pend = dep.deposit(key, ijk, vq, pk, pv);
+                    }
                 }
             }
             if (MODE) {
@@ -915,9 +927,11 @@ __global__ void k_finalize(uint64_t N, const float* nH, const float* xn, const u
 // FP64 and the two values per cell go through the same LDS cache as the
 // forward deposits, as FP64 or as 64-bit fixed point.
 template <int NB, bool DET>
-__global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
+// Three wavefronts per SIMD (at most 168 VGPRs); the registers this spills are
+// outside the walk loop.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_adjoint(AdjArgs a, int level) {
     using V = typename std::conditional<DET, unsigned long long, double>::type;
-    using Dep = Deposit<2, V>;
+    using Dep = Deposit<2, V, kAdjointSlots>;
     extern __shared__ __align__(16) unsigned char adj_lds[];
     const Geo& g = a.g;
     Counters* ct = a.ct;
@@ -1056,7 +1070,7 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a, int level) {
 template <int NB, bool DET>
 size_t adjoint_lds_bytes(unsigned block) {
     using V = typename std::conditional<DET, unsigned long long, double>::type;
-    return (size_t)(block / kWave) * Deposit<2, V>::kBytes;
+    return (size_t)(block / kWave) * Deposit<2, V, kAdjointSlots>::kBytes;
 }
 
 // Convert the accumulated dL/dn_H and dL/dx_n to the FP32 outputs.
@@ -1386,7 +1400,8 @@ SweepArgs sweep_args(art_ctx* c, const float* nH, const float* xn, const double*
 template <bool DET, int MODE>
 size_t sweep_lds_bytes(unsigned block) {
     return MODE ? (size_t)(block / kWave) *
-                      Deposit<SweepVals<MODE>::NV, typename std::conditional<DET, unsigned long long, float>::type>::kBytes
+                      Deposit<SweepVals<MODE>::NV, typename std::conditional<DET, unsigned long long, float>::type,
+                              kSweepSlots>::kBytes
                 : 0;
 }
 

@@ -116,6 +116,7 @@ struct Ray {
     double r_end;     // r_split if the ray can split before leaving, else d_exit
     bool can_split;   // r_max(l) < d_exit (a tie exits)
     bool starts_outside;  // r_a >= d_exit: created outside the domain, no segment
+    uint32_t dc[3];   // change of the linear cell index for one step along axis a (in direction n)
 };
 
 __device__ inline void ray_setup(const Geo& g, const double* __restrict__ src_pos, uint32_t src,
@@ -128,6 +129,9 @@ __device__ inline void ray_setup(const Geo& g, const double* __restrict__ src_po
         r.n[a] = g.rot[3 * a + 0] * v[0] + g.rot[3 * a + 1] * v[1] + g.rot[3 * a + 2] * v[2];
         r.inv[a] = 1.0 / r.n[a];
     }
+    const uint32_t stride[3] = {1u, (uint32_t)g.nx, (uint32_t)g.nx * (uint32_t)g.ny};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r.dc[a] = r.n[a] > 0.0 ? stride[a] : 0u - stride[a];
     const double hi[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
     double d_exit = INFINITY;
 #pragma unroll
@@ -170,6 +174,19 @@ struct MarchState {
     int end;
 };
 
+// v_min_f64 / v_max_f64 without the NaN-quieting the compiler puts around
+// fmin / fmax: face parameters are finite or +-infinity, never NaN.
+__device__ __forceinline__ double min_f64(double x, double y) {
+    double r;
+    __asm__("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(x), "v"(y));
+    return r;
+}
+__device__ __forceinline__ double max_f64(double x, double y) {
+    double r;
+    __asm__("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(x), "v"(y));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t cell_index(const Geo& g, const int (&cell)[3]) {
     return ((uint32_t)cell[2] * (uint32_t)g.ny + (uint32_t)cell[1]) * (uint32_t)g.nx + (uint32_t)cell[0];
 }
@@ -208,11 +225,11 @@ __device__ __forceinline__ bool march_step(const Geo& g, const float2* __restric
     const bool alive = m.alive;
     const bool budget = m.it < m.max_steps;
     m.it += 1;
-    const double rb0 = fmin(fmin(m.tnext[0], m.tnext[1]), m.tnext[2]);
+    const double rb0 = min_f64(min_f64(m.tnext[0], m.tnext[1]), m.tnext[2]);
     const bool ends = !(rb0 < r.r_end);
     const double rb = ends ? r.r_end : rb0;
     dr = rb - m.rr;
-    const bool seg = alive && budget && dr > 0.0;
+    const bool seg = alive & budget & (dr > 0.0);
     c = m.c;
 #pragma unroll
     for (int a = 0; a < 3; ++a) ijk[a] = m.cell[a];
@@ -227,11 +244,11 @@ __device__ __forceinline__ bool march_step(const Geo& g, const float2* __restric
         tin[b] = tau[b];
         const double t1 = tau[b] + dtau[b];
         tau[b] = seg ? t1 : tau[b];
-        thick = thick && (t1 > g.tau_term);
+        thick = thick & (t1 > g.tau_term);
     }
     m.rr = seg ? rb : m.rr;
     // step every axis whose face is at rb (ties step together)
-    const bool go = alive && budget && !ends && !thick;
+    const bool go = alive & budget & !ends & !thick;
     bool moved = false, out = false;
     int nc[3];
     double nt[3];
@@ -243,26 +260,28 @@ __device__ __forceinline__ bool march_step(const Geo& g, const float2* __restric
         nc[a] = m.cell[a] + (up ? 1 : -1);
         const double face = (double)(up ? nc[a] + 1 : nc[a]);
         nt[a] = (face - r.xs[a]) * r.inv[a];
-        moved = moved || st[a];
-        out = out || (st[a] && (nc[a] < 0 || nc[a] >= dims[a]));  // rounding guard at the boundary
+        moved = moved | st[a];
+        // rounding guard at the boundary (the unsigned compare also catches nc < 0)
+        out = out | (st[a] & ((uint32_t)nc[a] >= (uint32_t)dims[a]));
     }
-    const bool adv = go && moved && !out;
+    const bool adv = go & moved & !out;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const bool s2 = adv && st[a];
+        const bool s2 = adv & st[a];
         m.cell[a] = s2 ? nc[a] : m.cell[a];
         m.tnext[a] = s2 ? nt[a] : m.tnext[a];
     }
-    const bool bad = alive && (!budget || (go && !moved));
-    *stuck = *stuck || bad;
-    const bool finish = alive && !adv;
+    const bool bad = alive & (!budget | (go & !moved));
+    *stuck = *stuck | bad;
+    const bool finish = alive & !adv;
     const int end_new = thick ? kTerm : ((ends && r.can_split) ? kSplit : kExit);
     m.end = finish ? end_new : m.end;
-    m.alive = alive && adv;
-    if (adv) {
-        m.c = cell_index(g, m.cell);
-        m.q = q[m.c];  // prefetch for the next step
-    }
+    m.alive = alive & adv;
+    uint32_t c2 = m.c;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c2 += (adv & st[a]) ? r.dc[a] : 0u;
+    m.c = c2;
+    if (adv) m.q = q[c2];  // prefetch for the next step
     return seg;
 }
 
@@ -275,7 +294,7 @@ __device__ __forceinline__ bool march_step(const Geo& g, const float2* __restric
 // here (the caller has the forward's end value).
 struct BackState {
     int cell[3];
-    int start[3];     // the forward walk's first cell (where the backward walk stops)
+    uint32_t start_c; // linear index of the forward walk's first cell (where the backward walk stops)
     double tprev[3];  // entry-face parameter of the current cell per axis
     double rhi;       // upper end of the current segment
     uint32_t c;
@@ -298,14 +317,16 @@ __device__ inline void back_begin(const Geo& g, const float2* __restrict__ q, co
     m.cell[1] = (int)(rem / (uint32_t)g.nx);
     m.cell[0] = (int)(rem - (uint32_t)m.cell[1] * (uint32_t)g.nx);
     const int dims[3] = {g.nx, g.ny, g.nz};
+    int start[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         m.tprev[a] = entry_face(r, a, m.cell[a]);
         // the start cell exactly as march_begin finds it
         const double p = r.xs[a] + r.r_a * r.n[a];
         int c = (int)floor(p);
-        m.start[a] = c < 0 ? 0 : (c > dims[a] - 1 ? dims[a] - 1 : c);
+        start[a] = c < 0 ? 0 : (c > dims[a] - 1 ? dims[a] - 1 : c);
     }
+    m.start_c = cell_index(g, start);
     m.rhi = r_last;
     m.c = last_cell;
     m.q = q[last_cell];
@@ -323,14 +344,13 @@ __device__ __forceinline__ bool back_step(const Geo& g, const float2* __restrict
     const bool alive = m.alive;
     const bool budget = m.it < m.max_steps;
     m.it += 1;
-    const double lo0 = fmax(fmax(m.tprev[0], m.tprev[1]), m.tprev[2]);
+    const double lo0 = max_f64(max_f64(m.tprev[0], m.tprev[1]), m.tprev[2]);
     // the ray's first segment: the forward's start cell (whose entry face can lie a
     // rounding error beyond r_a), or an entry face at or before r_a
-    const bool first = (m.cell[0] == m.start[0] && m.cell[1] == m.start[1] && m.cell[2] == m.start[2]) ||
-                       !(lo0 > r.r_a);
+    const bool first = (m.c == m.start_c) | !(lo0 > r.r_a);
     const double rlo = first ? r.r_a : lo0;
     dr = m.rhi - rlo;
-    const bool seg = alive && budget && dr > 0.0;
+    const bool seg = alive & budget & (dr > 0.0);
     c = m.c;
 #pragma unroll
     for (int a = 0; a < 3; ++a) ijk[a] = m.cell[a];
@@ -340,7 +360,7 @@ __device__ __forceinline__ bool back_step(const Geo& g, const float2* __restrict
     if (NB > 1) kap[NB - 1] = dnH * g.s_d;
 #pragma unroll
     for (int b = 0; b < NB; ++b) dtau[b] = kap[b] * dr;
-    const bool go = alive && budget && !first;
+    const bool go = alive & budget & !first;
     bool moved = false, out = false;
     int nc[3];
     bool st[3];
@@ -348,23 +368,24 @@ __device__ __forceinline__ bool back_step(const Geo& g, const float2* __restrict
     for (int a = 0; a < 3; ++a) {
         st[a] = m.tprev[a] == lo0;
         nc[a] = m.cell[a] - (r.n[a] > 0.0 ? 1 : -1);
-        moved = moved || st[a];
-        out = out || (st[a] && (nc[a] < 0 || nc[a] >= dims[a]));
+        moved = moved | st[a];
+        out = out | (st[a] & ((uint32_t)nc[a] >= (uint32_t)dims[a]));
     }
-    const bool adv = go && moved && !out;
+    const bool adv = go & moved & !out;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const bool s2 = adv && st[a];
+        const bool s2 = adv & st[a];
         m.cell[a] = s2 ? nc[a] : m.cell[a];
         m.tprev[a] = s2 ? entry_face(r, a, nc[a]) : m.tprev[a];
     }
     m.rhi = adv ? lo0 : m.rhi;
-    *stuck = *stuck || (alive && (!budget || (go && (!moved || out))));
-    m.alive = alive && adv;
-    if (adv) {
-        m.c = cell_index(g, m.cell);
-        m.q = q[m.c];
-    }
+    *stuck = *stuck | (alive & (!budget | (go & (!moved | out))));
+    m.alive = alive & adv;
+    uint32_t c2 = m.c;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c2 -= (adv & st[a]) ? r.dc[a] : 0u;
+    m.c = c2;
+    if (adv) m.q = q[c2];
     return seg;
 }
 
