@@ -319,7 +319,9 @@ struct Deposit {
     using V = V_;  // float, double, or unsigned 64-bit fixed point (two's complement sums)
     static constexpr int S = S_;           // cache slots: 128 or 256
     static_assert(S_ == 128 || S_ == 256, "the slot map is an 8 x 8 x (S/64) tile");
+    static constexpr int W = NV;           // values per slot
     static constexpr int CAP = 128;        // staging capacity (>= 64 + flush threshold)
+    static constexpr uint32_t kFlushAt = CAP - kWave;
     // Staging row stride: the flush reads rows f = 0..3 at one column each; a
     // stride of 144 words puts those rows 16 (FP32) or 32 (64-bit) banks apart.
     static constexpr int CAPP = CAP + 16;
@@ -471,6 +473,148 @@ struct Deposit {
     }
 };
 
+// A slot holding a group of G cells, G g .. G g + G - 1, whose values are
+// adjacent in the AoS accumulator (G = 2 in the forward sweep's fixed point:
+// one 64-byte segment of two cells x four 8-byte values; G = 4 in the adjoint:
+// four cells x two values).  Memory-side atomics cost per request, and the
+// lanes of one flush instruction on one segment make one request, so an evicted
+// group reaches memory in one request; neighbouring cells along x also share a
+// slot, which cuts the evictions themselves.  The staging list holds single
+// cells; a group is staged as G consecutive entries from a position that is a
+// multiple of G, so the flush keeps a group in one instruction.
+template <int NV, class V_, int G_>
+struct GroupDeposit {
+    using V = V_;
+    static constexpr int G = G_;
+    static_assert(G == 2 || G == 4, "groups of 2 or 4 cells");
+    static constexpr int S = 64;           // slots: a 4 x 4 x 4 tile of (i / G, j, k)
+    static constexpr int W = G * NV;       // values per slot (cell G g first)
+    static constexpr int CAP = G * kWave + 16;  // staged cells: a step adds at most G x 64
+    static constexpr uint32_t kFlushAt = CAP - G * kWave;
+    static constexpr int CAPP = CAP + 16;
+    static constexpr int LPE = NV <= 2 ? 2 : (NV <= 4 ? 4 : 8);
+    static_assert((kWave / LPE) % G == 0, "a flush instruction covers whole groups");
+    static constexpr size_t kBytes = sizeof(V) * ((size_t)W * S + (size_t)NV * CAPP) + sizeof(uint32_t) * (S + CAP);
+    ART_LDS uint32_t* keys;                // [S]: group index g, or kEmptyKey
+    ART_LDS V* vals;                       // [W][S]: value q of cell G g + s in slot h at (s * NV + q) * S + h
+    ART_LDS uint32_t* skey;                // [CAP]
+    ART_LDS V* sval;                       // [NV][CAPP]
+    uint32_t n_staged;                     // wave-uniform, a multiple of G
+
+    __device__ static inline GroupDeposit at(unsigned char* base) {
+        ART_LDS unsigned char* b = (ART_LDS unsigned char*)base;
+        ART_LDS V* v = (ART_LDS V*)b;
+        ART_LDS V* sv = v + (size_t)W * S;
+        ART_LDS uint32_t* k = (ART_LDS uint32_t*)(sv + (size_t)NV * CAPP);
+        return GroupDeposit{k, v, k + S, sv, 0u};
+    }
+    __device__ static inline uint32_t slot(const int (&ijk)[3]) {
+        return (uint32_t)(((ijk[0] / G) & 3) | ((ijk[1] & 3) << 2) | ((ijk[2] & 3) << 4));
+    }
+    using D = Deposit<NV, V, 128>;
+
+    __device__ inline void init(int lane) {
+        for (int s = lane; s < S; s += kWave) keys[s] = kEmptyKey;
+        n_staged = 0u;
+        D::lds_order();
+    }
+
+    // Active lanes only.  As Deposit::deposit, keyed by the group; a winner
+    // starts its slot with its own values in its part and zeros elsewhere.
+    // Returns true if the group (pk, pv) must be staged.
+    __device__ inline bool deposit(uint32_t c, const int (&ijk)[3], const V (&v)[NV], uint32_t& pk, V (&pv)[W]) {
+        const uint32_t g = c / (uint32_t)G;
+        const uint32_t part = c % (uint32_t)G;
+        const uint32_t own = part * (uint32_t)NV;
+        const uint32_t h = slot(ijk);
+        ART_LDS V* sv = vals + h;
+        const uint32_t key0 = keys[h];
+        const bool hit = key0 == g;
+        if (hit) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) D::lds_add(&sv[(own + q) * S], v[q]);
+        }
+        D::lds_order();
+        bool pend = false;
+        uint32_t prev = key0;
+        if (!hit) prev = atomicCAS((uint32_t*)&keys[h], key0, g);
+        const bool won = !hit && prev == key0;
+        if (won) {
+            pk = key0;
+            pend = key0 != kEmptyKey;
+#pragma unroll
+            for (int w = 0; w < W; ++w) pv[w] = sv[w * S];
+#pragma unroll
+            for (int s = 0; s < G; ++s)
+#pragma unroll
+                for (int q = 0; q < NV; ++q) sv[(s * NV + q) * S] = (uint32_t)s == part ? v[q] : (V)0;
+        }
+        D::lds_order();
+        const bool follower = !hit && !won && prev == g;
+        if (follower) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) D::lds_add(&sv[(own + q) * S], v[q]);
+        }
+        if (!hit && !won && !follower) {
+            pk = g;
+#pragma unroll
+            for (int s = 0; s < G; ++s)
+#pragma unroll
+                for (int q = 0; q < NV; ++q) pv[s * NV + q] = (uint32_t)s == part ? v[q] : (V)0;
+            pend = true;
+        }
+        D::lds_order();
+        return pend;
+    }
+
+    // Converged: append the pending groups (G entries each) to the staging list.
+    __device__ inline void stage(bool pend, uint32_t pk, const V (&pv)[W]) {
+        const unsigned long long mk = __ballot(pend);
+        D::lds_order();
+        if (pend) {
+            const uint32_t e = n_staged + (uint32_t)G * (uint32_t)__builtin_amdgcn_mbcnt_hi(
+                                                           (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+#pragma unroll
+            for (int s = 0; s < G; ++s) {
+                skey[e + s] = (uint32_t)G * pk + (uint32_t)s;
+#pragma unroll
+                for (int q = 0; q < NV; ++q) sval[q * CAPP + e + s] = pv[s * NV + q];
+            }
+        }
+        n_staged += (uint32_t)G * (uint32_t)__popcll(mk);
+        D::lds_order();
+    }
+
+    // Converged: as Deposit::flush (kWave / LPE cells, whole groups, per instruction).
+    __device__ inline void flush(V* acc, int lane, uint32_t threshold) {
+        const uint32_t n = n_staged;
+        if (n < threshold || n == 0) return;
+        const uint32_t per = kWave / LPE;
+        const int f = lane % LPE;
+        for (uint32_t b0 = 0; b0 < n; b0 += per) {
+            const uint32_t e = b0 + (uint32_t)lane / LPE;
+            if (e < n && f < NV) D::global_add(acc + (uint64_t)skey[e] * LPE + f, sval[f * CAPP + e]);
+        }
+        n_staged = 0u;
+        D::lds_order();
+    }
+
+    // Converged: empty the cache into the accumulator.
+    __device__ inline void drain(V* acc, int lane) {
+        for (int s0 = 0; s0 < S; s0 += kWave) {
+            const int s = s0 + lane;
+            const uint32_t k = keys[s];
+            V old[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) old[w] = vals[w * S + s];
+            stage(k != kEmptyKey, k, old);
+            keys[s] = kEmptyKey;
+            D::lds_order();
+            flush(acc, lane, 1u);
+        }
+    }
+};
+
 // --------------------------------------------------------------------------
 // Forward sweep of one level
 // --------------------------------------------------------------------------
@@ -506,21 +650,37 @@ __device__ __forceinline__ void quad_combine(int lane, uint32_t& key, float (&v)
     }
 }
 
+// A wavefront claims 64 consecutive rays of a level with one atomic; lane l
+// takes base + l.  The order matters: the quad pre-combine pairs sibling rays
+// (four consecutive rays of a level) by lane.  Every lane of the wavefront must
+// be present.
+__device__ __forceinline__ uint32_t claim_rays(uint32_t* head, int lane) {
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(head, (uint32_t)kWave);
+    return (uint32_t)__builtin_amdgcn_readlane((int)base, 0) + (uint32_t)lane;
+}
+
 template <int MODE>
 struct SweepVals {
     static constexpr int NV = MODE == 2 ? 5 : 4;
 };
-// Forward deposits: a 128-slot cache keeps a wavefront's LDS at 9.5 KB (64-bit
-// values), so 16 wavefronts fit a CU; the adjoint keeps 256 slots.
-constexpr int kSweepSlots = 128;
-constexpr int kAdjointSlots = 256;
+// Forward deposits: pairs of cells per slot in fixed point, where memory-side
+// atomic requests are the cost; single cells (128 slots) with FP32 atomics,
+// where LDS float atomics are.  Either keeps a wavefront's LDS under 10 KB, so
+// 16 wavefronts fit a CU.  The adjoint keeps 256 single-cell slots.
+template <int NV, bool DET>
+using SweepDeposit = typename std::conditional<DET, GroupDeposit<NV, unsigned long long, 2>, Deposit<NV, float, 128>>::type;
+// Adjoint deposits (two values per cell): 256 single-cell slots.  Grouped slots
+// (four cells) were slower here: the adjoint is not bound by memory-side atomics.
+template <bool DET>
+using AdjointDeposit = Deposit<2, typename std::conditional<DET, unsigned long long, double>::type, 256>;
 
 template <int NB, bool DET, int MODE>
 // Four wavefronts per SIMD (at most 128 VGPRs): the march is latency bound, and
 // the few registers this spills are outside the loop.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_sweep(SweepArgs a, int level) {
     constexpr int NV = SweepVals<MODE>::NV;
-    using Dep = Deposit<NV, typename std::conditional<DET, unsigned long long, float>::type, kSweepSlots>;
+    using Dep = SweepDeposit<NV, DET>;
     using V = typename Dep::V;
     // Dynamic LDS: Dep::kBytes per wavefront of the workgroup (none in MODE 0)
     extern __shared__ __align__(16) unsigned char sweep_lds[];
@@ -551,12 +711,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     };
 
     for (;;) {
-        // Every lane claims one ray.  The uniform-address atomic is combined by
-        // the compiler into one atomic per wavefront (consecutive indices), and
-        // the loop exit is a wave-uniform ballot, so the loop stays a single
-        // convergent loop (no lane waits on a value another lane computes under
-        // a divergent branch).
-        const uint32_t li = atomicAdd(&ct->w.head[level], 1u);
+        // Every lane claims one ray, and the loop exit is a wave-uniform ballot,
+        // so the loop stays a single convergent loop (no lane waits on a value
+        // another lane computes under a divergent branch).
+        const uint32_t li = claim_rays(&ct->w.head[level], lane);
         const bool active = li < n_level;
         if (__ballot(active) == 0ull) break;
         const uint64_t slot = off + (active ? li : 0u);
@@ -600,7 +758,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         auto step = [&]() __attribute__((always_inline)) {
             bool pend = false;
             uint32_t pk = 0;
-            V pv[NV];
+            V pv[Dep::W];
             {
                 uint32_t c;
                 int ijk[3];
@@ -645,7 +803,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             }
             if (MODE) {
                 dep.stage(pend, pk, pv);
-                dep.flush(acc, lane, (uint32_t)(Dep::CAP - kWave));
+                dep.flush(acc, lane, Dep::kFlushAt);
             }
         };
         while (__ballot(m.alive)) {
@@ -931,7 +1089,7 @@ template <int NB, bool DET>
 // outside the walk loop.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_adjoint(AdjArgs a, int level) {
     using V = typename std::conditional<DET, unsigned long long, double>::type;
-    using Dep = Deposit<2, V, kAdjointSlots>;
+    using Dep = AdjointDeposit<DET>;
     extern __shared__ __align__(16) unsigned char adj_lds[];
     const Geo& g = a.g;
     Counters* ct = a.ct;
@@ -953,7 +1111,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     };
 
     for (;;) {
-        const uint32_t li = atomicAdd(&ct->w.adj_head[level], 1u);
+        const uint32_t li = claim_rays(&ct->w.adj_head[level], lane);
         const bool active = li < n_level;
         if (__ballot(active) == 0ull) break;
         const uint64_t slot = off + (active ? li : 0u);
@@ -1000,7 +1158,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         auto step = [&]() __attribute__((always_inline)) {
             bool pend = false;
             uint32_t pk = 0;
-            V pv[2];
+            V pv[Dep::W];
             {
                 uint32_t c;
                 int ijk[3];
@@ -1049,7 +1207,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 if (seg) pend = dep.deposit(c, ijk, v, pk, pv);
             }
             dep.stage(pend, pk, pv);
-            dep.flush(acc, lane, (uint32_t)(Dep::CAP - kWave));
+            dep.flush(acc, lane, Dep::kFlushAt);
         };
         while (__ballot(m.alive)) {
             step();
@@ -1069,8 +1227,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 
 template <int NB, bool DET>
 size_t adjoint_lds_bytes(unsigned block) {
-    using V = typename std::conditional<DET, unsigned long long, double>::type;
-    return (size_t)(block / kWave) * Deposit<2, V, kAdjointSlots>::kBytes;
+    return (size_t)(block / kWave) * AdjointDeposit<DET>::kBytes;
 }
 
 // Convert the accumulated dL/dn_H and dL/dx_n to the FP32 outputs.
@@ -1400,8 +1557,7 @@ SweepArgs sweep_args(art_ctx* c, const float* nH, const float* xn, const double*
 template <bool DET, int MODE>
 size_t sweep_lds_bytes(unsigned block) {
     return MODE ? (size_t)(block / kWave) *
-                      Deposit<SweepVals<MODE>::NV, typename std::conditional<DET, unsigned long long, float>::type,
-                              kSweepSlots>::kBytes
+                      SweepDeposit<SweepVals<MODE>::NV, DET>::kBytes
                 : 0;
 }
 
@@ -1606,7 +1762,8 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
     if (ok && o.enable_adjoint)
         ok = dmalloc(&c->pool.child, cap) && dmalloc(&c->pool.G, 2 * cap) && dmalloc(&c->pool.last, cap) &&
              dmalloc(&c->pool.rlast, cap) && dmalloc(&c->pool.taulast, 2 * cap);
-    if (ok) ok = det ? dmalloc(&c->det, 8 * N) : dmalloc(&c->acc, 8 * N);
+    // one spare cell: the sweep's deposit cache flushes cells in pairs (2g, 2g + 1)
+    if (ok) ok = det ? dmalloc(&c->det, 8 * (N + 1)) : dmalloc(&c->acc, 8 * (N + 1));
     if (ok) ok = dmalloc(&c->q, N);
     if (ok && o.enable_adjoint) ok = det ? dmalloc(&c->gdet, 2 * N) : dmalloc(&c->gk, 2 * N);
     if (ok && o.enable_adjoint) ok = dmalloc(&c->wv, N);
@@ -1652,9 +1809,10 @@ int art_trace(art_ctx* c, const float* n_H, const float* x_n, const double* src_
     if ((rc = begin_call(c, src_lum, n_src, n_H, x_n))) return rc;
     const int mode = (J && c->p.n_bins > 1) ? 2 : 1;
     const int lpe = mode == 2 ? 8 : 4;
+    const uint64_t n_acc = N + (N & 1);  // whole pairs
     if (det) {
-        if ((rc = zero(c, c->det, (uint64_t)lpe * N))) return rc;
-    } else if ((rc = zero(c, c->acc, (uint64_t)lpe * N))) {
+        if ((rc = zero(c, c->det, (uint64_t)lpe * n_acc))) return rc;
+    } else if ((rc = zero(c, c->acc, (uint64_t)lpe * n_acc))) {
         return rc;
     }
     if ((rc = zero(c, c->st.created, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.split, ms * ART_MAX_LEVELS)) ||
