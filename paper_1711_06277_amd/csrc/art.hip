@@ -479,37 +479,41 @@ struct Deposit {
 // four cells x two values).  Memory-side atomics cost per request, and the
 // lanes of one flush instruction on one segment make one request, so an evicted
 // group reaches memory in one request; neighbouring cells along x also share a
-// slot, which cuts the evictions themselves.  The staging list holds single
-// cells; a group is staged as G consecutive entries from a position that is a
-// multiple of G, so the flush keeps a group in one instruction.
+// slot, which cuts the evictions themselves.  The staging list holds groups
+// (one key, and the values in planes by value and cell, so consecutive groups
+// are consecutive words); a flush instruction covers whole groups.
 template <int NV, class V_, int G_>
 struct GroupDeposit {
     using V = V_;
     static constexpr int G = G_;
     static_assert(G == 2 || G == 4, "groups of 2 or 4 cells");
-    static constexpr int S = 64;           // slots: a 4 x 4 x 4 tile of (i / G, j, k)
+    static constexpr int S = 64;           // slots: a 4 x 4 x 4 tile of (i / G, j, k), folded
     static constexpr int W = G * NV;       // values per slot (cell G g first)
     static constexpr int CAP = G * kWave + 16;  // staged cells: a step adds at most G x 64
     static constexpr uint32_t kFlushAt = CAP - G * kWave;
-    static constexpr int CAPP = CAP + 16;
+    static constexpr int CAPG = CAP / G;                  // staged groups
+    static constexpr int CAPH = CAPG + 4;                 // plane stride
     static constexpr int LPE = NV <= 2 ? 2 : (NV <= 4 ? 4 : 8);
     static_assert((kWave / LPE) % G == 0, "a flush instruction covers whole groups");
-    static constexpr size_t kBytes = sizeof(V) * ((size_t)W * S + (size_t)NV * CAPP) + sizeof(uint32_t) * (S + CAP);
+    static constexpr size_t kBytes = sizeof(V) * ((size_t)W * S + (size_t)W * CAPH) + sizeof(uint32_t) * (S + CAPG);
     ART_LDS uint32_t* keys;                // [S]: group index g, or kEmptyKey
     ART_LDS V* vals;                       // [W][S]: value q of cell G g + s in slot h at (s * NV + q) * S + h
-    ART_LDS uint32_t* skey;                // [CAP]
-    ART_LDS V* sval;                       // [NV][CAPP]
-    uint32_t n_staged;                     // wave-uniform, a multiple of G
+    ART_LDS uint32_t* skey;                // [CAPG]: staged group keys
+    ART_LDS V* sval;                       // [NV][G][CAPH]: value q of cell s of staged group p at (q * G + s) * CAPH + p
+    uint32_t n_staged;                     // staged cells, wave-uniform, a multiple of G
 
     __device__ static inline GroupDeposit at(unsigned char* base) {
         ART_LDS unsigned char* b = (ART_LDS unsigned char*)base;
         ART_LDS V* v = (ART_LDS V*)b;
         ART_LDS V* sv = v + (size_t)W * S;
-        ART_LDS uint32_t* k = (ART_LDS uint32_t*)(sv + (size_t)NV * CAPP);
+        ART_LDS uint32_t* k = (ART_LDS uint32_t*)(sv + (size_t)W * CAPH);
         return GroupDeposit{k, v, k + S, sv, 0u};
     }
+    // k's bits folded into the i bits (a bijection): with 8-byte rows of 64
+    // slots, slots 32 apart share LDS banks.
     __device__ static inline uint32_t slot(const int (&ijk)[3]) {
-        return (uint32_t)(((ijk[0] / G) & 3) | ((ijk[1] & 3) << 2) | ((ijk[2] & 3) << 4));
+        const uint32_t h = (uint32_t)(((ijk[0] / G) & 3) | ((ijk[1] & 3) << 2) | ((ijk[2] & 3) << 4));
+        return h ^ ((h >> 4) & 3u);
     }
     using D = Deposit<NV, V, 128>;
 
@@ -544,10 +548,19 @@ struct GroupDeposit {
             pend = key0 != kEmptyKey;
 #pragma unroll
             for (int w = 0; w < W; ++w) pv[w] = sv[w * S];
+            if constexpr (G == 2) {
+                const uint32_t other = (uint32_t)NV - own;
 #pragma unroll
-            for (int s = 0; s < G; ++s)
+                for (int q = 0; q < NV; ++q) {
+                    sv[(own + q) * S] = v[q];
+                    sv[(other + q) * S] = (V)0;
+                }
+            } else {
 #pragma unroll
-                for (int q = 0; q < NV; ++q) sv[(s * NV + q) * S] = (uint32_t)s == part ? v[q] : (V)0;
+                for (int s = 0; s < G; ++s)
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) sv[(s * NV + q) * S] = (uint32_t)s == part ? v[q] : (V)0;
+            }
         }
         D::lds_order();
         const bool follower = !hit && !won && prev == g;
@@ -572,14 +585,13 @@ struct GroupDeposit {
         const unsigned long long mk = __ballot(pend);
         D::lds_order();
         if (pend) {
-            const uint32_t e = n_staged + (uint32_t)G * (uint32_t)__builtin_amdgcn_mbcnt_hi(
-                                                           (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+            const uint32_t p = n_staged / (uint32_t)G + (uint32_t)__builtin_amdgcn_mbcnt_hi(
+                                                          (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+            skey[p] = pk;
 #pragma unroll
-            for (int s = 0; s < G; ++s) {
-                skey[e + s] = (uint32_t)G * pk + (uint32_t)s;
+            for (int q = 0; q < NV; ++q)
 #pragma unroll
-                for (int q = 0; q < NV; ++q) sval[q * CAPP + e + s] = pv[s * NV + q];
-            }
+                for (int s = 0; s < G; ++s) sval[(q * G + s) * CAPH + p] = pv[s * NV + q];
         }
         n_staged += (uint32_t)G * (uint32_t)__popcll(mk);
         D::lds_order();
@@ -593,7 +605,9 @@ struct GroupDeposit {
         const int f = lane % LPE;
         for (uint32_t b0 = 0; b0 < n; b0 += per) {
             const uint32_t e = b0 + (uint32_t)lane / LPE;
-            if (e < n && f < NV) D::global_add(acc + (uint64_t)skey[e] * LPE + f, sval[f * CAPP + e]);
+            const uint32_t p = e / (uint32_t)G, s = e % (uint32_t)G;
+            if (e < n && f < NV)
+                D::global_add(acc + ((uint64_t)skey[p] * G + s) * LPE + f, sval[(f * G + s) * CAPH + p]);
         }
         n_staged = 0u;
         D::lds_order();
