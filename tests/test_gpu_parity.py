@@ -92,6 +92,24 @@ def test_deterministic_mode_bitwise(oracle):
     assert np.array_equal(r1, r2) and np.array_equal(f1, f2) and np.array_equal(J1, J2)
 
 
+def test_deterministic_odd_cell_count(oracle):
+    """Fixed-point deposits on a grid with an odd number of cells (33 x 31 x 35):
+    the deposit cache flushes cells in pairs (2g, 2g + 1), so the last cell's pair
+    reaches the accumulator's spare cell.  With J (five values per cell) and
+    without (four), against the oracle; rate and force are bitwise equal
+    between the two."""
+    wl = small_lognormal(nx=33, ny=31, nz=35, n_src=3, seed=9)
+    assert (wl.nx * wl.ny * wl.nz) % 2 == 1
+    ref, (rate5, force5, _), _ = check_against_oracle(oracle, wl, deterministic=True)
+    (rate4, force4), st = run_gpu(wl, want_J=False, deterministic=True)
+    assert st.status == 0
+    assert np.array_equal(rate4, rate5) and np.array_equal(force4, force5)
+    L_tot = float(wl.src_lum.astype(np.float64).sum())
+    compare_cells("rate", rate4, ref.rate, L_tot)
+    # the last cell (whose pair partner is the spare cell) is reached by rays
+    assert ref.J[0][-1] > 0 and rate4[-1] > 0
+
+
 def test_many_waves_match_one_wave(oracle):
     """A pool that holds one source at a time (several waves) gives the same
     tree and cells as the oracle."""
