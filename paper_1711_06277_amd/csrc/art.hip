@@ -1194,17 +1194,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                         // transmission at the segment's entry: E(out) / e^{-dtau}, or
                         // directly where either underflows
                         tau[b] -= x;
-                        double Ein = E[b] / e;
+                        double Ein = E[b] * rcp_f64(e);
                         if (!(E[b] > 1e-290 && e > 1e-290)) Ein = exp(-tau[b]);
                         E[b] = Ein;
                         const double Lin = lnom[b] * Ein;
                         double own = beta * Lin * om;
                         double dk = beta * Lin * dr * e;
                         if (b == 0) {
-                            const double ph = absorb_phi(x, om);
+                            double ph, dph;
+                            absorb_phi_dphi(x, e, om, ph, dph);
                             j0 = Lin * dr * ph;
                             own += wa * j0;
-                            dk += wa * Lin * dr * dr * absorb_dphi(x, e, om);
+                            dk += wa * Lin * dr * dr * dph;
                         }
                         dkap[b] = dk - dr * (A[b] + Gend[b]);
                         A[b] += own;

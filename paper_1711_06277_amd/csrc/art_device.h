@@ -400,16 +400,24 @@ __device__ __forceinline__ void absorb_factors(float x, float& phi, float& one_m
     one_minus_e = small ? x * ser : ome;
 }
 
-// FP64 versions for the adjoint: phi(x) = (1 - e^{-x})/x given om = 1 - e^{-x},
-// and phi'(x) = (x e^{-x} - (1 - e^{-x}))/x^2, with series near 0.
-__device__ __forceinline__ double absorb_phi(double x, double om) {
-    if (x < 1e-3) return 1.0 - x * (0.5 - x * (1.0 / 6.0 - x * (1.0 / 24.0)));
-    return om / x;
+// 1/d for normal d: the hardware estimate refined by two Newton steps (about
+// 1 ulp), cheaper than a correctly rounded division.
+__device__ __forceinline__ double rcp_f64(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double t = fma(-d, r, 1.0);
+    r = fma(r, t, r);
+    t = fma(-d, r, 1.0);
+    return fma(r, t, r);
 }
 
-__device__ __forceinline__ double absorb_dphi(double x, double e, double om) {
-    if (x < 1e-3) return -0.5 + x * (1.0 / 3.0 - x * (0.125 - x * (1.0 / 30.0)));
-    return (x * e - om) / (x * x);
+// FP64 versions for the adjoint: phi(x) = (1 - e^{-x})/x and
+// phi'(x) = (x e^{-x} - (1 - e^{-x}))/x^2, given e = e^{-x} and om = 1 - e^{-x},
+// with one reciprocal of x; series below 1e-3 (where x may be 0).
+__device__ __forceinline__ void absorb_phi_dphi(double x, double e, double om, double& phi, double& dphi) {
+    const bool small = x < 1e-3;
+    const double r = rcp_f64(small ? 1.0 : x);
+    phi = small ? 1.0 - x * (0.5 - x * (1.0 / 6.0 - x * (1.0 / 24.0))) : om * r;
+    dphi = small ? -0.5 + x * (1.0 / 3.0 - x * (0.125 - x * (1.0 / 30.0))) : (x * e - om) * r * r;
 }
 
 // ---------------------------------------------------------------------------
