@@ -38,11 +38,17 @@ def log(*a):
 
 
 def kernel_sources_sha() -> str:
+    """Hash of the kernel sources' code: comments and blank space are dropped, so
+    a comment edit keeps the committed counter summaries valid."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("paper_1711_06277_amd/csrc/art.hip", "paper_1711_06277_amd/csrc/art_device.h"):
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -474,14 +474,14 @@ struct Deposit {
 };
 
 // A slot holding a group of G cells, G g .. G g + G - 1, whose values are
-// adjacent in the AoS accumulator (G = 2 in the forward sweep's fixed point:
-// one 64-byte segment of two cells x four 8-byte values; G = 4 in the adjoint:
-// four cells x two values).  Memory-side atomics cost per request, and the
-// lanes of one flush instruction on one segment make one request, so an evicted
-// group reaches memory in one request; neighbouring cells along x also share a
-// slot, which cuts the evictions themselves.  The staging list holds groups
-// (one key, and the values in planes by value and cell, so consecutive groups
-// are consecutive words); a flush instruction covers whole groups.
+// adjacent in the AoS accumulator (the forward sweep's fixed point uses G = 2:
+// one 64-byte segment of two cells x four 8-byte values).  Memory-side atomics
+// cost per request, and the lanes of one flush instruction on one segment make
+// one request, so an evicted group reaches memory in one request; neighbouring
+// cells along x also share a slot, which cuts the evictions themselves.  The
+// staging list holds groups (one key, and the values in planes by value and
+// cell, so consecutive groups are consecutive words); a flush instruction
+// covers whole groups.
 template <int NV, class V_, int G_>
 struct GroupDeposit {
     using V = V_;
