@@ -110,6 +110,23 @@ def test_deterministic_odd_cell_count(oracle):
     assert ref.J[0][-1] > 0 and rate4[-1] > 0
 
 
+@pytest.mark.parametrize("deterministic", [False, True])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 6, 5), (3, 1, 2), (5, 4, 1)])
+def test_degenerate_grids(oracle, shape, deterministic):
+    """Grids one cell thick (or a single cell, N odd): cells pair up across rows
+    and with the accumulator's spare cell.  Tree, cells and conservation against
+    the oracle."""
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    rng = np.random.default_rng(n)
+    pos = np.stack([rng.uniform(0.1, nx - 0.1, 2), rng.uniform(0.1, ny - 0.1, 2), rng.uniform(0.1, nz - 0.1, 2)], 1)
+    wl = I.Workload(name=f"degenerate {nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz,
+                    n_H=rng.uniform(0.5, 2.0, n).astype(np.float32),
+                    x_n=rng.uniform(0.0, 1.0, n).astype(np.float32), src_pos=pos,
+                    src_lum=np.array([[1.0, 0.5], [3.0, 2.0]], dtype=np.float32), s_H=0.3, s_d=0.03, n_bins=2)
+    check_against_oracle(oracle, wl, deterministic=deterministic)
+
+
 def test_many_waves_match_one_wave(oracle):
     """A pool that holds one source at a time (several waves) gives the same
     tree and cells as the oracle."""
