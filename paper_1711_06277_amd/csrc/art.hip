@@ -16,10 +16,11 @@
 //     same radial shell [r_max(l-1), r_max(l)], so the lanes of a wavefront do
 //     similar amounts of work.
 //   * Geometry, tau and all tree decisions in FP64; the per-segment deposit
-//     arithmetic in FP32.  Deposits are merged per wavefront in an LDS cache and
-//     flushed with coalesced global atomics: FP32, or 64-bit fixed-point integers
-//     in the deterministic mode (integer sums do not depend on the order, so
-//     results are bitwise reproducible, and LDS integer atomics are also faster).
+//     arithmetic in FP32.  Deposits are merged per wavefront in an LDS cache of
+//     64-bit fixed-point partial sums (LDS integer atomics are fast) and flushed
+//     with coalesced global atomics: 64-bit integers in the deterministic mode
+//     (integer sums do not depend on the order, so results are bitwise
+//     reproducible), FP32 otherwise.
 //   * The destroy counter of Sec. 2.2 (a ray ended at level l adds
 //     4^(l_max - l)) is kept as a device-side completeness check of the tree.
 //   * No allocation, host synchronisation or memset node inside art_trace /
@@ -597,8 +598,16 @@ struct GroupDeposit {
         D::lds_order();
     }
 
+    // Memory-side addition of one staged value: as is into a fixed-point
+    // accumulator, or converted (times inv, the inverse scale) into an FP32 one.
+    __device__ static inline void acc_add(unsigned long long* p, unsigned long long x, double) { atomicAdd(p, x); }
+    __device__ static inline void acc_add(float* p, unsigned long long x, double inv) {
+        unsafeAtomicAdd(p, (float)((double)(long long)x * inv));
+    }
+
     // Converged: as Deposit::flush (kWave / LPE cells, whole groups, per instruction).
-    __device__ inline void flush(V* acc, int lane, uint32_t threshold) {
+    template <class A>
+    __device__ inline void flush(A* acc, int lane, uint32_t threshold, double inv) {
         const uint32_t n = n_staged;
         if (n < threshold || n == 0) return;
         const uint32_t per = kWave / LPE;
@@ -607,14 +616,15 @@ struct GroupDeposit {
             const uint32_t e = b0 + (uint32_t)lane / LPE;
             const uint32_t p = e / (uint32_t)G, s = e % (uint32_t)G;
             if (e < n && f < NV)
-                D::global_add(acc + ((uint64_t)skey[p] * G + s) * LPE + f, sval[(f * G + s) * CAPH + p]);
+                acc_add(acc + ((uint64_t)skey[p] * G + s) * LPE + f, sval[(f * G + s) * CAPH + p], inv);
         }
         n_staged = 0u;
         D::lds_order();
     }
 
     // Converged: empty the cache into the accumulator.
-    __device__ inline void drain(V* acc, int lane) {
+    template <class A>
+    __device__ inline void drain(A* acc, int lane, double inv) {
         for (int s0 = 0; s0 < S; s0 += kWave) {
             const int s = s0 + lane;
             const uint32_t k = keys[s];
@@ -624,7 +634,7 @@ struct GroupDeposit {
             stage(k != kEmptyKey, k, old);
             keys[s] = kEmptyKey;
             D::lds_order();
-            flush(acc, lane, 1u);
+            flush(acc, lane, 1u, inv);
         }
     }
 };
@@ -634,7 +644,8 @@ struct GroupDeposit {
 // --------------------------------------------------------------------------
 
 // MODE 0: tree only (the tape pass of the adjoint); 1: J0 and the force;
-// 2: also J1 (the non-ionizing bin's J).  DET: 64-bit fixed-point deposits.
+// 2: also J1 (the non-ionizing bin's J).  DET: a 64-bit fixed-point
+// accumulator, else FP32 (the LDS partial sums are fixed point in both).
 // Quad pre-combine (DPP lane moves, no LDS): lanes 4k..4k+3 of a wavefront trace
 // the four children of one parent pixel and often cross the same cell in the same
 // step.  Partners lane^1 and then lane^2 compare keys; on a match the lower lane
@@ -678,12 +689,12 @@ template <int MODE>
 struct SweepVals {
     static constexpr int NV = MODE == 2 ? 5 : 4;
 };
-// Forward deposits: pairs of cells per slot in fixed point, where memory-side
-// atomic requests are the cost; single cells (128 slots) with FP32 atomics,
-// where LDS float atomics are.  Either keeps a wavefront's LDS under 10 KB, so
-// 16 wavefronts fit a CU.  The adjoint keeps 256 single-cell slots.
-template <int NV, bool DET>
-using SweepDeposit = typename std::conditional<DET, GroupDeposit<NV, unsigned long long, 2>, Deposit<NV, float, 128>>::type;
+// Forward deposits, both modes: pairs of cells per slot, partial sums in 64-bit
+// fixed point in LDS (integer LDS atomics are fast, float ones are not), one
+// memory request per evicted pair.  The FP32 mode converts a staged value to
+// FP32 at the flush.  9.8 KB of LDS per wavefront: 16 wavefronts fit a CU.
+template <int NV>
+using SweepDeposit = GroupDeposit<NV, unsigned long long, 2>;
 // Adjoint deposits (two values per cell): 256 single-cell slots.  Grouped slots
 // (four cells) were slower here: the adjoint is not bound by memory-side atomics.
 template <bool DET>
@@ -694,7 +705,7 @@ template <int NB, bool DET, int MODE>
 // the few registers this spills are outside the loop.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_sweep(SweepArgs a, int level) {
     constexpr int NV = SweepVals<MODE>::NV;
-    using Dep = SweepDeposit<NV, DET>;
+    using Dep = SweepDeposit<NV>;
     using V = typename Dep::V;
     // Dynamic LDS: Dep::kBytes per wavefront of the workgroup (none in MODE 0)
     extern __shared__ __align__(16) unsigned char sweep_lds[];
@@ -710,19 +721,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const uint64_t off_next = off + n_level;
     const int next = level + 1;
     if (blockIdx.x == 0 && threadIdx.x == 0 && next <= ART_MAX_LEVELS) ct->w.off[next] = off_next;
-    const double scale = DET ? ct->c.scale : 0.0;
+    const double scale = ct->c.scale;
+    const double inv_scale = 1.0 / scale;  // a power of two
     const float lnom_scale = ldexpf(1.0f / 12.0f, -2 * level);  // 1 / N_ray(l)
     const unsigned long long dweight = 1ull << (2 * (g.level_max - level));
-    V* acc = (V*)(DET ? (void*)a.det : (void*)a.acc);
+    using Acc = typename std::conditional<DET, unsigned long long, float>::type;
+    Acc* acc = (Acc*)(DET ? (void*)a.det : (void*)a.acc);
 
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     Dep dep = Dep::at(sweep_lds + (MODE ? (size_t)w * Dep::kBytes : 0));
     if (MODE) dep.init(lane);
 
-    auto quant = [&](float x) -> V {
-        if (DET) return (V)(unsigned long long)fixed_point(x, scale);
-        else return (V)x;
-    };
+    auto quant = [&](float x) -> V { return (V)(unsigned long long)fixed_point(x, scale); };
 
     for (;;) {
         // Every lane claims one ray, and the loop exit is a wave-uniform ballot,
@@ -817,7 +827,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             }
             if (MODE) {
                 dep.stage(pend, pk, pv);
-                dep.flush(acc, lane, Dep::kFlushAt);
+                dep.flush(acc, lane, Dep::kFlushAt, inv_scale);
             }
         };
         while (__ballot(m.alive)) {
@@ -901,7 +911,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             }
         }
     }
-    if (MODE) dep.drain(acc, lane);
+    if (MODE) dep.drain(acc, lane, inv_scale);
 }
 
 // --------------------------------------------------------------------------
@@ -1572,7 +1582,7 @@ SweepArgs sweep_args(art_ctx* c, const float* nH, const float* xn, const double*
 template <bool DET, int MODE>
 size_t sweep_lds_bytes(unsigned block) {
     return MODE ? (size_t)(block / kWave) *
-                      SweepDeposit<SweepVals<MODE>::NV, DET>::kBytes
+                      SweepDeposit<SweepVals<MODE>::NV>::kBytes
                 : 0;
 }
 
