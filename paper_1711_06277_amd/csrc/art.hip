@@ -315,9 +315,21 @@ __global__ void k_seed(Pool pool, Counters* ct, int level0, int src0, int n_wave
 constexpr uint32_t kEmptyKey = 0xffffffffu;
 #define ART_LDS __attribute__((address_space(3)))
 
+// LDS atomic add at wavefront scope (a cache belongs to one wavefront).
+template <class T>
+__device__ __forceinline__ void lds_add(ART_LDS T* p, T x) {
+    __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ void global_add(double* p, double x) { unsafeAtomicAdd(p, x); }
+__device__ __forceinline__ void global_add(unsigned long long* p, unsigned long long x) { atomicAdd(p, x); }
+
+// Compiler-only barrier: LDS operations of different lanes in different
+// branches are not reordered across it.
+__device__ __forceinline__ void lds_order() { __asm__ volatile("" ::: "memory"); }
+
 template <int NV, class V_, int S_>
 struct Deposit {
-    using V = V_;  // float, double, or unsigned 64-bit fixed point (two's complement sums)
+    using V = V_;  // double, or unsigned 64-bit fixed point (two's complement sums)
     static constexpr int S = S_;           // cache slots: 128 or 256
     static_assert(S_ == 128 || S_ == 256, "the slot map is an 8 x 8 x (S/64) tile");
     static constexpr int W = NV;           // values per slot
@@ -352,23 +364,6 @@ struct Deposit {
         const uint32_t h = (uint32_t)((ijk[0] & 7) | ((ijk[1] & 7) << 3) | ((ijk[2] & (S / 64 - 1)) << 6));
         return h ^ ((h >> 4) & (uint32_t)(S / 16 - 1));
     }
-    __device__ static inline void lds_add(ART_LDS float* p, float x) {
-        __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    }
-    __device__ static inline void lds_add(ART_LDS double* p, double x) {
-        __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    }
-    __device__ static inline void lds_add(ART_LDS unsigned long long* p, unsigned long long x) {
-        __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    }
-    __device__ static inline void global_add(float* p, float x) { unsafeAtomicAdd(p, x); }
-    __device__ static inline void global_add(double* p, double x) { unsafeAtomicAdd(p, x); }
-    __device__ static inline void global_add(unsigned long long* p, unsigned long long x) { atomicAdd(p, x); }
-
-    // Compiler-only barrier: LDS operations of different lanes in different
-    // branches are not reordered across it.
-    __device__ static inline void lds_order() { __asm__ volatile("" ::: "memory"); }
-
     __device__ inline void init(int lane) {
         for (int s = lane; s < S; s += kWave) keys[s] = kEmptyKey;
         n_staged = 0u;
@@ -516,12 +511,11 @@ struct GroupDeposit {
         const uint32_t h = (uint32_t)(((ijk[0] / G) & 3) | ((ijk[1] & 3) << 2) | ((ijk[2] & 3) << 4));
         return h ^ ((h >> 4) & 3u);
     }
-    using D = Deposit<NV, V, 128>;
 
     __device__ inline void init(int lane) {
         for (int s = lane; s < S; s += kWave) keys[s] = kEmptyKey;
         n_staged = 0u;
-        D::lds_order();
+        lds_order();
     }
 
     // Active lanes only.  As Deposit::deposit, keyed by the group; a winner
@@ -537,9 +531,9 @@ struct GroupDeposit {
         const bool hit = key0 == g;
         if (hit) {
 #pragma unroll
-            for (int q = 0; q < NV; ++q) D::lds_add(&sv[(own + q) * S], v[q]);
+            for (int q = 0; q < NV; ++q) lds_add(&sv[(own + q) * S], v[q]);
         }
-        D::lds_order();
+        lds_order();
         bool pend = false;
         uint32_t prev = key0;
         if (!hit) prev = atomicCAS((uint32_t*)&keys[h], key0, g);
@@ -563,11 +557,11 @@ struct GroupDeposit {
                     for (int q = 0; q < NV; ++q) sv[(s * NV + q) * S] = (uint32_t)s == part ? v[q] : (V)0;
             }
         }
-        D::lds_order();
+        lds_order();
         const bool follower = !hit && !won && prev == g;
         if (follower) {
 #pragma unroll
-            for (int q = 0; q < NV; ++q) D::lds_add(&sv[(own + q) * S], v[q]);
+            for (int q = 0; q < NV; ++q) lds_add(&sv[(own + q) * S], v[q]);
         }
         if (!hit && !won && !follower) {
             pk = g;
@@ -577,14 +571,14 @@ struct GroupDeposit {
                 for (int q = 0; q < NV; ++q) pv[s * NV + q] = (uint32_t)s == part ? v[q] : (V)0;
             pend = true;
         }
-        D::lds_order();
+        lds_order();
         return pend;
     }
 
     // Converged: append the pending groups (G entries each) to the staging list.
     __device__ inline void stage(bool pend, uint32_t pk, const V (&pv)[W]) {
         const unsigned long long mk = __ballot(pend);
-        D::lds_order();
+        lds_order();
         if (pend) {
             const uint32_t p = n_staged / (uint32_t)G + (uint32_t)__builtin_amdgcn_mbcnt_hi(
                                                           (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
@@ -595,7 +589,7 @@ struct GroupDeposit {
                 for (int s = 0; s < G; ++s) sval[(q * G + s) * CAPH + p] = pv[s * NV + q];
         }
         n_staged += (uint32_t)G * (uint32_t)__popcll(mk);
-        D::lds_order();
+        lds_order();
     }
 
     // Memory-side addition of one staged value: as is into a fixed-point
@@ -619,7 +613,7 @@ struct GroupDeposit {
                 acc_add(acc + ((uint64_t)skey[p] * G + s) * LPE + f, sval[(f * G + s) * CAPH + p], inv);
         }
         n_staged = 0u;
-        D::lds_order();
+        lds_order();
     }
 
     // Converged: empty the cache into the accumulator.
@@ -633,7 +627,7 @@ struct GroupDeposit {
             for (int w = 0; w < W; ++w) old[w] = vals[w * S + s];
             stage(k != kEmptyKey, k, old);
             keys[s] = kEmptyKey;
-            D::lds_order();
+            lds_order();
             flush(acc, lane, 1u, inv);
         }
     }
