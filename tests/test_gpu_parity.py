@@ -110,6 +110,35 @@ def test_deterministic_odd_cell_count(oracle):
     assert ref.J[0][-1] > 0 and rate4[-1] > 0
 
 
+def test_deterministic_independent_of_launch_shape():
+    """Fixed-point results do not depend on the launch shape: a wavefront claims 64
+    consecutive rays of a level whatever the workgroup size and grid, so the
+    pre-combine pairs the same sibling rays, and the integer sums are exact.
+    Forward (rate, force, J) and adjoint gradients are bitwise equal across shapes."""
+    import torch
+    from paper_1711_06277_amd.api import ArtTracer
+    wl = small_lognormal(nx=36, ny=30, nz=34, n_src=4, seed=17)
+    rng = np.random.default_rng(5)
+    w = rng.uniform(-1, 1, wl.nx * wl.ny * wl.nz).astype(np.float32)
+    v = rng.uniform(-1, 1, (3, wl.nx * wl.ny * wl.nz)).astype(np.float32)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    results = []
+    for block, per_cu in ((64, 16), (256, 4), (128, 1), (192, 3)):
+        tr = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins, tau_term=wl.tau_term,
+                       deterministic=True, enable_adjoint=True, max_sources=wl.n_src,
+                       block_size=block, blocks_per_cu=per_cu)
+        try:
+            args = (dev(wl.n_H), dev(wl.x_n), dev(wl.src_pos), dev(wl.src_lum))
+            rate, force, J = tr.trace(*args, want_J=True)
+            g_nH, g_xn = tr.adjoint(*args, dev(w), dev(v))
+            results.append([t.cpu().numpy() for t in (rate, force, J, g_nH, g_xn)])
+        finally:
+            tr.close()
+    for other in results[1:]:
+        for a, b in zip(results[0], other):
+            assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("deterministic", [False, True])
 @pytest.mark.parametrize("shape", [(1, 1, 1), (1, 6, 5), (3, 1, 2), (5, 4, 1)])
 def test_degenerate_grids(oracle, shape, deterministic):
