@@ -1,0 +1,54 @@
+"""Host logic of bench.py (no GPU): the kernel-source hash that decides whether the
+committed counter summaries still describe the built kernels, and the lookup of
+the measured traffic."""
+import os
+import shutil
+
+import pytest
+
+import bench
+
+
+@pytest.fixture
+def src_copy(tmp_path, monkeypatch):
+    """bench's ROOT pointed at a scratch copy of the two kernel sources."""
+    for f in ("paper_1711_06277_amd/csrc/art.hip", "paper_1711_06277_amd/csrc/art_device.h"):
+        dst = tmp_path / f
+        dst.parent.mkdir(parents=True, exist_ok=True)
+        shutil.copy(os.path.join(bench.ROOT, f), dst)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    return tmp_path
+
+
+def _edit(path, fn):
+    text = path.read_text()
+    path.write_text(fn(text))
+
+
+def test_hash_ignores_comments_and_blank_space(src_copy):
+    h0 = bench.kernel_sources_sha()
+    hip = src_copy / "paper_1711_06277_amd/csrc/art.hip"
+    _edit(hip, lambda t: "// a new comment line\n" + t.replace("\n\n", "\n\n\n", 3) + "\n/* block\n comment */\n")
+    assert bench.kernel_sources_sha() == h0
+
+
+def test_hash_follows_code_changes(src_copy):
+    h0 = bench.kernel_sources_sha()
+    dev = src_copy / "paper_1711_06277_amd/csrc/art_device.h"
+    _edit(dev, lambda t: t.replace("kStStuck = 4", "kStStuck = 16", 1))
+    assert bench.kernel_sources_sha() != h0
+
+
+def test_measured_traffic_needs_matching_sources(src_copy):
+    """The committed summary's traffic is reported for the sources it was taken
+    on, and withheld (None) once the code differs."""
+    prof = src_copy / "profiles"
+    prof.mkdir()
+    for name in ("k_sweep_c3_traffic.md", "k_sweep_c3_atomic_traffic.md"):
+        shutil.copy(os.path.join(os.path.dirname(os.path.abspath(bench.__file__)), "profiles", name), prof / name)
+    for det in (True, False):
+        t = bench.measured_traffic(3, det)
+        assert t is not None and t > 0
+    assert bench.measured_traffic(5, True) is None
+    _edit(src_copy / "paper_1711_06277_amd/csrc/art.hip", lambda t: t + "\nstatic int art_unused_marker = 1;\n")
+    assert bench.measured_traffic(3, True) is None
