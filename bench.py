@@ -96,7 +96,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sweep is not "
-              "sharded across GPUs in this build", file=sys.stderr)
+              "sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
