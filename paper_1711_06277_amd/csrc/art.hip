@@ -332,6 +332,7 @@ struct Deposit {
     using V = V_;  // double, or unsigned 64-bit fixed point (two's complement sums)
     static constexpr int S = S_;           // cache slots: 128 or 256
     static_assert(S_ == 128 || S_ == 256, "the slot map is an 8 x 8 x (S/64) tile");
+    static_assert(S % kWave == 0, "init and drain walk the slots a wavefront at a time");
     static constexpr int W = NV;           // values per slot
     static constexpr int CAP = 128;        // staging capacity (>= 64 + flush threshold)
     static constexpr uint32_t kFlushAt = CAP - kWave;
@@ -484,6 +485,7 @@ struct GroupDeposit {
     static constexpr int G = G_;
     static_assert(G == 2 || G == 4, "groups of 2 or 4 cells");
     static constexpr int S = 64;           // slots: a 4 x 4 x 4 tile of (i / G, j, k), folded
+    static_assert(S % kWave == 0, "init and drain walk the slots a wavefront at a time");
     static constexpr int W = G * NV;       // values per slot (cell G g first)
     static constexpr int CAP = G * kWave + 16;  // staged cells: a step adds at most G x 64
     static constexpr uint32_t kFlushAt = CAP - G * kWave;
