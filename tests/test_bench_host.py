@@ -40,15 +40,23 @@ def test_hash_follows_code_changes(src_copy):
 
 
 def test_measured_traffic_needs_matching_sources(src_copy):
-    """The committed summary's traffic is reported for the sources it was taken
-    on, and withheld (None) once the code differs."""
+    """A counter summary's traffic is reported for the sources it was taken on,
+    and withheld (None) once the code differs."""
     prof = src_copy / "profiles"
     prof.mkdir()
-    for name in ("k_sweep_c3_traffic.md", "k_sweep_c3_atomic_traffic.md"):
-        shutil.copy(os.path.join(os.path.dirname(os.path.abspath(bench.__file__)), "profiles", name), prof / name)
-    for det in (True, False):
-        t = bench.measured_traffic(3, det)
-        assert t is not None and t > 0
-    assert bench.measured_traffic(5, True) is None
+    sha = bench.kernel_sources_sha()
+    for name, val in (("k_sweep_c3_traffic.md", 1.5e11), ("k_sweep_c3_atomic_traffic.md", 1.25e11)):
+        (prof / name).write_text(f"# summary\n\ntraffic_bytes_per_trace: {val:.6e}\nkernel_sources_sha: {sha}\n")
+    assert bench.measured_traffic(3, True) == 1.5e11
+    assert bench.measured_traffic(3, False) == 1.25e11
+    assert bench.measured_traffic(5, True) is None  # only the 256^3 workload is profiled
     _edit(src_copy / "paper_1711_06277_amd/csrc/art.hip", lambda t: t + "\nstatic int art_unused_marker = 1;\n")
     assert bench.measured_traffic(3, True) is None
+
+
+def test_committed_summaries_are_readable():
+    """The committed summaries carry the two fields bench.py reads."""
+    for name in ("k_sweep_c3_traffic.md", "k_sweep_c3_atomic_traffic.md"):
+        with open(os.path.join(bench.ROOT, "profiles", name)) as fh:
+            text = fh.read()
+        assert "traffic_bytes_per_trace:" in text and "kernel_sources_sha:" in text
