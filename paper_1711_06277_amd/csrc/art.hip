@@ -1195,8 +1195,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         const double x = dtau[b];
-                        const double om = -expm1(-x);
-                        const double e = 1.0 - om;
+                        double e, om;
+                        exp_neg(x, e, om);
                         // transmission at the segment's entry: E(out) / e^{-dtau}, or
                         // directly where either underflows
                         tau[b] -= x;

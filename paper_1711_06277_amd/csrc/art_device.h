@@ -410,6 +410,44 @@ __device__ __forceinline__ double rcp_f64(double d) {
     return fma(r, t, r);
 }
 
+// a * b + c as one three-operand v_fma_f64: with a constant c held in a
+// register, the compiler's two-operand form would copy c first at every use.
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+    double r;
+    __asm__("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// e = e^{-x} and om = 1 - e^{-x} in FP64 for x >= 0 (any size), by Cody and
+// Waite's reduction: e^{-x} = 2^{-k} e^{y}, k = rint(x / ln 2),
+// y = k ln 2 - x in [-ln2/2, ln2/2] with ln 2 in two parts (fused multiply-adds),
+// and e^{y} - 1 by its Taylor series to degree 14
+// (truncation below 1e-17 relative).  om = -(e^{y} - 1) when k = 0 (no
+// cancellation), else 1 - e >= 0.29.  Large x: 2^{-k} underflows to 0, om to 1.
+__device__ __forceinline__ void exp_neg(double x, double& e, double& om) {
+    const double kd = rint(x * 1.4426950408889634);
+    double y = fma(kd, 0x1.62e42feep-1, -x);
+    y = fma(kd, 0x1.a39ef35793c76p-33, y);
+    double p = 1.0 / 87178291200.0;  // 1/14!
+    p = fma3(p, y, 1.0 / 6227020800.0);
+    p = fma3(p, y, 1.0 / 479001600.0);
+    p = fma3(p, y, 1.0 / 39916800.0);
+    p = fma3(p, y, 1.0 / 3628800.0);
+    p = fma3(p, y, 1.0 / 362880.0);
+    p = fma3(p, y, 1.0 / 40320.0);
+    p = fma3(p, y, 1.0 / 5040.0);
+    p = fma3(p, y, 1.0 / 720.0);
+    p = fma3(p, y, 1.0 / 120.0);
+    p = fma3(p, y, 1.0 / 24.0);
+    p = fma3(p, y, 1.0 / 6.0);
+    p = fma(p, y, 0.5);
+    p = fma(p, y, 1.0);
+    p = p * y;  // e^{y} - 1
+    const int k = kd < 2.0e9 ? (int)kd : 2000000000;
+    e = ldexp(1.0 + p, -k);
+    om = kd == 0.0 ? -p : 1.0 - e;
+}
+
 // FP64 versions for the adjoint: phi(x) = (1 - e^{-x})/x and
 // phi'(x) = (x e^{-x} - (1 - e^{-x}))/x^2, given e = e^{-x} and om = 1 - e^{-x},
 // with one reciprocal of x; series below 1e-3 (where x may be 0).
