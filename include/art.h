@@ -62,7 +62,7 @@ typedef struct {
     int level0;          /* initial HEALPix level l0 (12*4^l0 rays per source) */
     int level_max;       /* deepest level; rays at level_max never split; < ART_MAX_LEVELS */
     double phi_c;        /* m_ray: split when (dx/r)^2 < m_ray * Omega_ray */
-    double tau_term;     /* destroy a ray once tau_b > tau_term in every bin */
+    double tau_term;     /* destroy a ray once tau_b > tau_term in every bin; 0 < tau_term < 5e5 */
     double s_H;          /* sigma_H * dx in code units: ionizing gas opacity per unit n_H x_n */
     double s_d;          /* sigma_d * dx in code units: dust opacity per unit n_H */
     int n_bins;          /* 1 (ionizing only) or 2 (ionizing, non-ionizing) */

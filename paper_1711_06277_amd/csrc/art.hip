@@ -1199,7 +1199,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                         exp_neg(x, e, om);
                         // transmission at the segment's entry: E(out) / e^{-dtau}, or
                         // directly where either underflows
-                        tau[b] -= x;
+                        tau[b] -= min_f64(x, kTauStep);
                         double Ein = E[b] * rcp_f64(e);
                         if (!(E[b] > 1e-290 && e > 1e-290)) Ein = exp(-tau[b]);
                         E[b] = Ein;
@@ -1504,7 +1504,8 @@ int check_params(const art_params* p) {
     if (p->level0 < 0 || p->level_max < p->level0 || p->level_max >= ART_MAX_LEVELS) return ART_ERR_INVALID_ARG;
     if (p->level_max > 14) return ART_ERR_INVALID_ARG;  // 12*4^l pixel ids must fit 32 bits
     if (p->n_bins < 1 || p->n_bins > ART_MAX_BINS) return ART_ERR_INVALID_ARG;
-    if (!(p->phi_c > 0.0) || !(p->tau_term > 0.0) || !(p->s_H >= 0.0) || !(p->s_d >= 0.0))
+    if (!(p->phi_c > 0.0) || !(p->tau_term > 0.0) || !(p->tau_term < 0.5 * kTauStep) || !(p->s_H >= 0.0) ||
+        !(p->s_d >= 0.0))
         return ART_ERR_INVALID_ARG;
     if (p->deposit_mode != ART_DEPOSIT_ATOMIC && p->deposit_mode != ART_DEPOSIT_DETERMINISTIC)
         return ART_ERR_INVALID_ARG;

@@ -187,6 +187,14 @@ __device__ __forceinline__ double max_f64(double x, double y) {
     return r;
 }
 
+// Largest optical-depth increment one segment adds to a ray's running tau.  The
+// transmission e^{-tau} is 0 in FP64 well before that, so no output changes,
+// while the running sums keep their earlier terms: the adjoint recovers a
+// segment's entry depth by subtracting its increment from the exit depth, which
+// a single increment of ~1e36 would otherwise reduce to zero.  Above any
+// termination depth art_create accepts.
+constexpr double kTauStep = 1.0e6;
+
 __device__ __forceinline__ uint32_t cell_index(const Geo& g, const int (&cell)[3]) {
     return ((uint32_t)cell[2] * (uint32_t)g.ny + (uint32_t)cell[1]) * (uint32_t)g.nx + (uint32_t)cell[0];
 }
@@ -242,7 +250,7 @@ __device__ __forceinline__ bool march_step(const Geo& g, const float2* __restric
     for (int b = 0; b < NB; ++b) {
         dtau[b] = kap[b] * dr;
         tin[b] = tau[b];
-        const double t1 = tau[b] + dtau[b];
+        const double t1 = tau[b] + min_f64(dtau[b], kTauStep);
         tau[b] = seg ? t1 : tau[b];
         thick = thick & (t1 > g.tau_term);
     }
@@ -423,8 +431,10 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
 // y = k ln 2 - x in [-ln2/2, ln2/2] with ln 2 in two parts (fused multiply-adds),
 // and e^{y} - 1 by its Taylor series to degree 14
 // (truncation below 1e-17 relative).  om = -(e^{y} - 1) when k = 0 (no
-// cancellation), else 1 - e >= 0.29.  Large x: 2^{-k} underflows to 0, om to 1.
+// cancellation), else 1 - e >= 0.29.  x is capped at 800 (e^{-800} is 0 in
+// FP64), so k stays small and y stays in range however large x is.
 __device__ __forceinline__ void exp_neg(double x, double& e, double& om) {
+    x = min_f64(x, 800.0);
     const double kd = rint(x * 1.4426950408889634);
     double y = fma(kd, 0x1.62e42feep-1, -x);
     y = fma(kd, 0x1.a39ef35793c76p-33, y);
@@ -443,8 +453,7 @@ __device__ __forceinline__ void exp_neg(double x, double& e, double& om) {
     p = fma(p, y, 0.5);
     p = fma(p, y, 1.0);
     p = p * y;  // e^{y} - 1
-    const int k = kd < 2.0e9 ? (int)kd : 2000000000;
-    e = ldexp(1.0 + p, -k);
+    e = ldexp(1.0 + p, -(int)kd);
     om = kd == 0.0 ? -p : 1.0 - e;
 }
 

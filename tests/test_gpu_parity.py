@@ -156,6 +156,39 @@ def test_degenerate_grids(oracle, shape, deterministic):
     check_against_oracle(oracle, wl, deterministic=deterministic)
 
 
+@pytest.mark.parametrize("deterministic", [False, True])
+def test_opaque_cells(oracle, deterministic):
+    """A block of very dense cells (n_H = 1e8: one segment's optical depth ~1e7,
+    above the cap on a segment's increment of the running depth) and one of
+    moderate thickness.  Tree bit for bit (rays end there by optical depth),
+    conservation, escaped / residual luminosity, and cells outside the dense
+    block to the parity bar; inside it the summed rate.  (In the dense cells
+    J = L_in / kappa is ~1e-10 L, a few 1e5 units of the fixed-point partial
+    sums, so single cells there carry that resolution.)"""
+    wl = small_lognormal(nx=24, ny=24, nz=24, n_src=2, seed=11)
+    nH = wl.n_H.reshape(24, 24, 24).copy()
+    nH[10:13, 4:7, 4:7] = 1.0e8
+    nH[4:6, 15:18, 12:14] = 1.0e4
+    wl.n_H = np.ascontiguousarray(nH.reshape(-1))
+    ref = oracle.trace_workload(wl)
+    (rate, force, J), st = run_gpu(wl, want_J=True, deterministic=deterministic)
+    assert st.status == 0
+    tree_equal(st, ref)
+    assert ref.terminated.sum() > 0
+    assert st.destroy == st.destroy_expected
+    cons = conservation(wl, J, st)
+    assert max(cons) <= CONS_TOL, f"photon conservation {cons}"
+    L_tot = float(wl.src_lum.astype(np.float64).sum())
+    np.testing.assert_allclose(st.src_escaped, ref.escaped, rtol=1e-5, atol=1e-12 * L_tot)
+    np.testing.assert_allclose(st.src_residual, ref.residual, rtol=1e-4, atol=1e-12 * L_tot)
+    dense = wl.n_H > 1e7
+    out = ~dense
+    compare_cells("rate", np.where(out, rate, 0.0), np.where(out, ref.rate, 0.0), L_tot)
+    for b in range(wl.n_bins):
+        compare_cells(f"J{b}", np.where(out, J[b], 0.0), np.where(out, ref.J[b], 0.0), L_tot)
+    assert abs(rate[dense].astype(np.float64).sum() / ref.rate[dense].sum() - 1) < 1e-4
+
+
 def test_many_waves_match_one_wave(oracle):
     """A pool that holds one source at a time (several waves) gives the same
     tree and cells as the oracle."""
