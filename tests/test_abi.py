@@ -69,3 +69,10 @@ def test_create_without_gpu_fails_cleanly():
     with pytest.raises(A.ArtError) as e:
         A.art_create(8, 8, 8, p, o, 0)
     assert e.value.code == A.ART_ERR_INVALID_ARG
+    # termination depths must stay below the cap on a segment's increment
+    o.max_sources = 1
+    for bad in (5.0e5, 1.0e30, float("inf"), float("nan"), 0.0):
+        p.tau_term = bad
+        with pytest.raises(A.ArtError) as e:
+            A.art_create(8, 8, 8, p, o, 0)
+        assert e.value.code == A.ART_ERR_INVALID_ARG, bad
