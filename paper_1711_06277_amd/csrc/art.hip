@@ -63,7 +63,7 @@ struct CallCounters {
     uint32_t status;
     uint32_t pad;
     double scale, inv_scale;      // forward fixed point: ~2^50 / L_total
-    double gscale, inv_gscale;    // adjoint fixed point
+    double gscale[2], inv_gscale[2];  // adjoint fixed point: dL/dn_H, dL/dx_n
 };
 
 struct Counters {
@@ -257,10 +257,15 @@ __global__ void k_adj_scale_final(Counters* ct, const float* src_lum, int n_lum,
     if (!(L > 0.0)) L = 1.0;
     double W = (double)scratch[0];
     if (!(W > 0.0)) W = 1.0;
-    const double chain = 1.0 + s_H + s_d + s_H * (double)scratch[1];
-    const double bound = 8.0 * W * L * chain;
-    ct->c.gscale = ldexp(1.0, 58) / bound;
-    ct->c.inv_gscale = bound * ldexp(1.0, -58);
+    // dL/dkappa_b of a segment is bounded without reference to n_H; dL/dn_H takes
+    // it times (x_n s_H + s_d) or s_d, dL/dx_n times n_H s_H, so only the latter
+    // bound carries the largest density
+    const double chain[2] = {1.0 + s_H + s_d, 1.0 + s_H + s_d + s_H * (double)scratch[1]};
+    for (int i = 0; i < 2; ++i) {
+        const double bound = 8.0 * W * L * chain[i];
+        ct->c.gscale[i] = ldexp(1.0, 58) / bound;
+        ct->c.inv_gscale[i] = bound * ldexp(1.0, -58);
+    }
 }
 
 // Seed a source wave: 12*4^l0 rays per source at level l0 (Sec. 2.1), source
@@ -1118,14 +1123,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     const uint64_t off = ct->w.off[level];
     const uint32_t n_level =
         (uint32_t)std::min<uint64_t>(ct->w.tail[level], a.pool.cap > off ? a.pool.cap - off : 0);
-    const double gscale = DET ? ct->c.gscale : 0.0;
+    const double gscale_n = DET ? ct->c.gscale[0] : 0.0, gscale_x = DET ? ct->c.gscale[1] : 0.0;
     const double inv_nray = 1.0 / (12.0 * ldexp(1.0, 2 * level));
     const double sH = g.s_H, sd = g.s_d;
     V* acc = (V*)(DET ? (void*)a.gdet : (void*)a.gk);
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     Dep dep = Dep::at(adj_lds + (size_t)w * Dep::kBytes);
     dep.init(lane);
-    auto quant = [&](double x) -> V {
+    auto quant = [&](double x, double gscale) -> V {
         if (DET) return (V)(unsigned long long)__double2ll_rn(x * gscale);
         else return (V)x;
     };
@@ -1222,8 +1227,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                     double gn = dkap[0] * (xv * sH + sd) + wj * xv;
                     if (NB > 1) gn += dkap[NB - 1] * sd;
                     const double gx = dkap[0] * nv * sH + wj * nv;
-                    v[0] = quant(gn);
-                    v[1] = quant(gx);
+                    v[0] = quant(gn, gscale_n);
+                    v[1] = quant(gx, gscale_x);
                 }
                 if (seg) pend = dep.deposit(c, ijk, v, pk, pv);
             }
@@ -1255,15 +1260,15 @@ size_t adjoint_lds_bytes(unsigned block) {
 template <bool DET>
 __global__ void k_adj_finalize(uint64_t N, const double* gk, const unsigned long long* gdet, const Counters* ct,
                                const uint8_t* transparent, float* g_nH, float* g_xn) {
-    const double ginv = DET ? ct->c.inv_gscale : 0.0;
+    const double ginv_n = DET ? ct->c.inv_gscale[0] : 0.0, ginv_x = DET ? ct->c.inv_gscale[1] : 0.0;
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N;
          c += (uint64_t)gridDim.x * blockDim.x) {
         if (transparent && transparent[c]) {  // the outputs do not depend on these fields
             g_nH[c] = 0.0f;
             g_xn[c] = 0.0f;
         } else if (DET) {
-            g_nH[c] = (float)((double)(long long)gdet[2 * c] * ginv);
-            g_xn[c] = (float)((double)(long long)gdet[2 * c + 1] * ginv);
+            g_nH[c] = (float)((double)(long long)gdet[2 * c] * ginv_n);
+            g_xn[c] = (float)((double)(long long)gdet[2 * c + 1] * ginv_x);
         } else {
             g_nH[c] = (float)gk[2 * c];
             g_xn[c] = (float)gk[2 * c + 1];
