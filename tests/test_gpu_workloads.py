@@ -28,12 +28,14 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def test_workload3_batched_full_size(oracle):
-    """256^3, 64 sources, 2 bins: per-source trees of sampled sources match the
-    oracle bit for bit; batched equals the sum of one-source calls; photon
-    conservation holds for the whole batch."""
+@pytest.mark.parametrize("deterministic", [True, False], ids=["fixed_point", "fp32_atomic"])
+def test_workload3_batched_full_size(oracle, deterministic):
+    """256^3, 64 sources, 2 bins, in both deposit modes (the benchmark times the
+    fixed-point one): per-source trees of sampled sources match the oracle bit for
+    bit; batched equals the sum of one-source calls; photon conservation holds for
+    the whole batch; in fixed point a second call is bitwise equal."""
     wl = I.config(3)
-    tr = tracer(wl, max_sources=wl.n_src)
+    tr = tracer(wl, max_sources=wl.n_src, deterministic=deterministic)
     nH, xn, pos, lum = dev(wl.n_H), dev(wl.x_n), dev(wl.src_pos), dev(wl.src_lum)
     try:
         rate, force, J = tr.trace(nH, xn, pos, lum, want_J=True)
@@ -53,9 +55,13 @@ def test_workload3_batched_full_size(oracle):
                                        atol=1e-12 * float(lum.sum()))
             assert abs(int(st.src_segments[s]) / int(ref.segments[0]) - 1) < 1e-4
         rate_b, force_b = rate.clone(), force.clone()
+        if deterministic:
+            J_b = J.clone()
+            rate2, force2, J2 = tr.trace(nH, xn, pos, lum, want_J=True)
+            assert torch.equal(rate2, rate_b) and torch.equal(force2, force_b) and torch.equal(J2, J_b)
     finally:
         tr.close()
-    tp = tracer(wl, max_sources=1)
+    tp = tracer(wl, max_sources=1, deterministic=deterministic)
     try:
         acc_r = torch.zeros_like(rate_b)
         acc_f = torch.zeros_like(force_b)
