@@ -332,6 +332,15 @@ __device__ __forceinline__ void global_add(unsigned long long* p, unsigned long 
 // branches are not reordered across it.
 __device__ __forceinline__ void lds_order() { __asm__ volatile("" ::: "memory"); }
 
+// A register the compiler treats as written, with no instruction: for values read
+// only on paths that assign them first.  Left undefined instead, such arrays are
+// zero-filled on every loop iteration, one move per register.
+template <class T> __device__ __forceinline__ T unset() {
+    T x;
+    __asm__ volatile("" : "=v"(x));
+    return x;
+}
+
 template <int NV, class V_, int S_>
 struct Deposit {
     using V = V_;  // double, or unsigned 64-bit fixed point (two's complement sums)
@@ -515,7 +524,7 @@ struct GroupDeposit {
     // k's bits folded into the i bits (a bijection): with 8-byte rows of 64
     // slots, slots 32 apart share LDS banks.
     __device__ static inline uint32_t slot(const int (&ijk)[3]) {
-        const uint32_t h = (uint32_t)(((ijk[0] / G) & 3) | ((ijk[1] & 3) << 2) | ((ijk[2] & 3) << 4));
+        const uint32_t h = (((uint32_t)ijk[0] / G) & 3u) | (((uint32_t)ijk[1] & 3u) << 2) | (((uint32_t)ijk[2] & 3u) << 4);
         return h ^ ((h >> 4) & 3u);
     }
 
@@ -781,9 +790,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         // The loop body twice per iteration: the march state then alternates
         // between two register sets instead of being copied back every step.
         auto step = [&]() __attribute__((always_inline)) {
+            // (pk, pv) are read only where deposit() returned true, which assigns them
             bool pend = false;
-            uint32_t pk = 0;
+            uint32_t pk = unset<uint32_t>();
             V pv[Dep::W];
+#pragma unroll
+            for (int w = 0; w < Dep::W; ++w) pv[w] = unset<V>();
             {
                 uint32_t c;
                 int ijk[3];
@@ -791,9 +803,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                 const bool seg = march_step<NB>(g, a.q, r, m, tau, &stuck, c, ijk, dr, dtau, tin);
                 if (seg) ++nseg;
                 if (MODE) {
+                    // without a segment the key below is empty: the quad combine
+                    // discards these values and nothing deposits them
                     float v[NV];
 #pragma unroll
-                    for (int q = 0; q < NV; ++q) v[q] = 0.0f;
+                    for (int q = 0; q < NV; ++q) v[q] = unset<float>();
                     if (seg) {
 #pragma clang fp contract(fast)
                         const float drf = (float)dr;
