@@ -501,7 +501,8 @@ struct GroupDeposit {
     static constexpr int S = 64;           // slots: a 4 x 4 x 4 tile of (i / G, j, k), folded
     static_assert(S % kWave == 0, "init and drain walk the slots a wavefront at a time");
     static constexpr int W = G * NV;       // values per slot (cell G g first)
-    static constexpr int CAP = G * kWave + 16;  // staged cells: a step adds at most G x 64
+    static constexpr int CAP = G * kWave + 16;  // staged cells: a step adds at most G x 64, and
+                                                // stages only after a flush left < kFlushAt
     static constexpr uint32_t kFlushAt = CAP - G * kWave;
     static constexpr int CAPG = CAP / G;                  // staged groups
     static constexpr int CAPH = CAPG + 4;                 // plane stride
@@ -632,7 +633,8 @@ struct GroupDeposit {
         lds_order();
     }
 
-    // Converged: empty the cache into the accumulator.
+    // Converged: empty the cache into the accumulator.  Fewer than kFlushAt cells
+    // may be staged on entry (each pass stages up to G x 64 more).
     template <class A>
     __device__ inline void drain(A* acc, int lane, double inv) {
         for (int s0 = 0; s0 < S; s0 += kWave) {
@@ -790,6 +792,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         // The loop body twice per iteration: the march state then alternates
         // between two register sets instead of being copied back every step.
         auto step = [&]() __attribute__((always_inline)) {
+            if (MODE) {
+                // Flush what earlier steps staged, but only after this step's gather
+                // has arrived: the vector-memory counter retires in order, so the
+                // next step's wait for its gather also waits for these atomics, and
+                // issued here they have a whole step to complete.
+                const float2 qv = m.q;
+                __asm__ volatile("" ::"v"(qv.x), "v"(qv.y));
+                dep.flush(acc, lane, Dep::kFlushAt, inv_scale);
+            }
             // (pk, pv) are read only where deposit() returned true, which assigns them
             bool pend = false;
             uint32_t pk = unset<uint32_t>();
@@ -840,10 +851,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                     }
                 }
             }
-            if (MODE) {
-                dep.stage(pend, pk, pv);
-                dep.flush(acc, lane, Dep::kFlushAt, inv_scale);
-            }
+            if (MODE) dep.stage(pend, pk, pv);
         };
         while (__ballot(m.alive)) {
             step();
@@ -926,7 +934,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             }
         }
     }
-    if (MODE) dep.drain(acc, lane, inv_scale);
+    if (MODE) {
+        dep.flush(acc, lane, 1u, inv_scale);
+        dep.drain(acc, lane, inv_scale);
+    }
 }
 
 // --------------------------------------------------------------------------
