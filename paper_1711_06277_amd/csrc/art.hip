@@ -468,7 +468,8 @@ struct Deposit {
         lds_order();
     }
 
-    // Converged: empty the cache into the accumulator.
+    // Converged: empty the cache into the accumulator.  Fewer than kFlushAt cells
+    // may be staged on entry (each pass stages up to 64 more).
     __device__ inline void drain(V* acc, int lane) {
         for (int s0 = 0; s0 < S; s0 += kWave) {
             const int s = s0 + lane;
@@ -1214,6 +1215,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 int ijk[3];
                 double dr, dtau[NB];
                 const float2 qc = m.q;
+                // as in the forward sweep: flush once this step's gather has arrived,
+                // so the atomics are not waited for by the loads that follow at once
+                __asm__ volatile("" ::"v"(qc.x), "v"(qc.y));
+                dep.flush(acc, lane, Dep::kFlushAt);
                 const bool seg = back_step<NB>(g, a.q, r, m, &stuck, c, ijk, dr, dtau);
                 V v[2] = {(V)0, (V)0};
                 if (seg) {
@@ -1258,7 +1263,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 if (seg) pend = dep.deposit(c, ijk, v, pk, pv);
             }
             dep.stage(pend, pk, pv);
-            dep.flush(acc, lane, Dep::kFlushAt);
         };
         while (__ballot(m.alive)) {
             step();
@@ -1273,6 +1277,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             for (int b = 0; b < NB; ++b) a.pool.G[2 * slot + b] = A[b] + Gend[b];
         }
     }
+    dep.flush(acc, lane, 1u);
     dep.drain(acc, lane);
 }
 
