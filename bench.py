@@ -52,24 +52,38 @@ def kernel_sources_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: int, deterministic: bool):
-    """HBM bytes per trace from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary (copy-calibrated), or None if the kernel has changed since."""
-    if workload != 3:
-        return None
-    name = "k_sweep_c3_traffic.md" if deterministic else "k_sweep_c3_atomic_traffic.md"
+def _summary_value(name: str, key: str):
+    """A value of a committed rocprofv3 summary, or None if the summary is missing
+    or was taken on other kernel sources."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     vals = {}
     with open(path) as fh:
         for line in fh:
-            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_trace", "kernel_sources_sha"):
+            if ":" in line and line.split(":")[0] in (key, "kernel_sources_sha"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_sources_sha") != kernel_sources_sha():
+    if vals.get("kernel_sources_sha") != kernel_sources_sha() or key not in vals:
         return None
-    return float(vals["traffic_bytes_per_trace"])
+    return float(vals[key])
+
+
+def measured_traffic(workload: int, deterministic: bool):
+    """HBM bytes per trace of the forward sweep from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None if the kernel has
+    changed since."""
+    if workload != 3:
+        return None
+    name = "k_sweep_c3_traffic.md" if deterministic else "k_sweep_c3_atomic_traffic.md"
+    return _summary_value(name, "traffic_bytes_per_trace")
+
+
+def measured_adjoint_traffic(workload: int, deterministic: bool):
+    """HBM bytes per adjoint sweep, likewise (profiled in the fixed-point mode)."""
+    if workload != 3 or not deterministic:
+        return None
+    return _summary_value("k_adjoint_c3_traffic.md", "traffic_bytes_per_adjoint")
 
 
 def main():
@@ -275,12 +289,16 @@ def main():
         ta.close()
         adj_s = t_adj / args.steps
         adj_gbs = segments * ADJOINT_BYTES_PER_SEGMENT / adj_s / 1e9
+        adj_traffic = measured_adjoint_traffic(args.workload, wl.deterministic)
         adjoint = {"ms_per_adjoint": 1e3 * adj_s,
                    "ms_per_forward_with_tree": 1e3 * t_fwd / args.steps,
                    "segments_per_s": segments / adj_s,
                    "status": rc, "gradients_finite": finite, "graph": graph,
                    "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "frac": adj_gbs / HBM_PEAK_GBS,
+                                "traffic": None if adj_traffic is None else adj_traffic / 1e9,
+                                "traffic_unit": "GB per adjoint sweep (sum over the per-level k_adjoint "
+                                                "launches), rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated",
                                 "kernel": "k_adjoint (one launch per level, deepest first; "
                                           "one backward walk over every segment)",
                                 "bytes_per_segment": ADJOINT_BYTES_PER_SEGMENT}}

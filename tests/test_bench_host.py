@@ -50,13 +50,19 @@ def test_measured_traffic_needs_matching_sources(src_copy):
     assert bench.measured_traffic(3, True) == 1.5e11
     assert bench.measured_traffic(3, False) == 1.25e11
     assert bench.measured_traffic(5, True) is None  # only the 256^3 workload is profiled
+    (prof / "k_adjoint_c3_traffic.md").write_text(f"# summary\n\ntraffic_bytes_per_adjoint: 2.5e11\nkernel_sources_sha: {sha}\n")
+    assert bench.measured_adjoint_traffic(3, True) == 2.5e11
+    assert bench.measured_adjoint_traffic(3, False) is None  # the adjoint is profiled in fixed point
     _edit(src_copy / "paper_1711_06277_amd/csrc/art.hip", lambda t: t + "\nstatic int art_unused_marker = 1;\n")
     assert bench.measured_traffic(3, True) is None
+    assert bench.measured_adjoint_traffic(3, True) is None
 
 
 def test_committed_summaries_are_readable():
     """The committed summaries carry the two fields bench.py reads."""
-    for name in ("k_sweep_c3_traffic.md", "k_sweep_c3_atomic_traffic.md"):
+    for name, key in (("k_sweep_c3_traffic.md", "traffic_bytes_per_trace:"),
+                      ("k_sweep_c3_atomic_traffic.md", "traffic_bytes_per_trace:"),
+                      ("k_adjoint_c3_traffic.md", "traffic_bytes_per_adjoint:")):
         with open(os.path.join(bench.ROOT, "profiles", name)) as fh:
             text = fh.read()
-        assert "traffic_bytes_per_trace:" in text and "kernel_sources_sha:" in text
+        assert key in text and "kernel_sources_sha:" in text
