@@ -1337,7 +1337,11 @@ __global__ void __launch_bounds__(256) k_ion_minq(uint64_t N, const float* nH, c
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int k = 1; k < (int)(blockDim.x / kWave); ++k) q = fmin(q, part[k]);
-        atomicMin(&ion[0], (unsigned long long)__double_as_longlong(q));
+        // Same-address atomics serialise; the running minimum only decreases, so a
+        // block whose value is not below a (possibly stale) read of it can skip its
+        // atomic.  Non-negative doubles order like their bit patterns.
+        const unsigned long long qb = (unsigned long long)__double_as_longlong(q);
+        if (qb < __hip_atomic_load(&ion[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(&ion[0], qb);
     }
 }
 
@@ -2171,8 +2175,10 @@ int art_ion_substep(art_ctx* c, const float* n_H, float* x_n, const double* src_
     if (rc) return rc;
     const uint64_t N = c->N;
     const dim3 fg(fill_blocks(N)), fb(256);
+    // the minimum: a few cells per thread and one atomic per block at most
+    const dim3 mg(std::min(fill_blocks(N), 1024));
     hipLaunchKernelGGL(k_ion_begin, dim3(1), dim3(64), 0, c->stream, c->ion);
-    hipLaunchKernelGGL(k_ion_minq, fg, fb, 0, c->stream, N, n_H, (const float*)x_n, (const float*)J, c->transparent,
+    hipLaunchKernelGGL(k_ion_minq, mg, fb, 0, c->stream, N, n_H, (const float*)x_n, (const float*)J, c->transparent,
                        ip->gamma_scale, ip->alpha_B, c->ion);
     hipLaunchKernelGGL(k_ion_dt, dim3(1), dim3(64), 0, c->stream, c->ion, ip->C, t_end, t_now);
     hipLaunchKernelGGL(k_ion_update, fg, fb, 0, c->stream, N, n_H, x_n, (const float*)J, (const float*)force,
