@@ -71,6 +71,10 @@ struct Counters {
     CallCounters c;
 };
 
+// Parents per tile of the child scan: whole claims of kWave rays.
+constexpr int kSplitTile = 4096;
+static_assert(kSplitTile % kWave == 0, "a claim lies in one tile");
+
 // The ray pool, structure of arrays.
 struct Pool {
     uint32_t* src;    // source index
@@ -85,7 +89,8 @@ struct Pool {
     uint32_t* last;
     double* rlast;
     double* taulast;  // [cap][2]
-    uint32_t* tsum;   // children per tile of kSplitTile parents, then their exclusive prefix
+    uint32_t* tsum;   // splitting rays per tile of kSplitTile parents (counted by the sweep), then
+                      // their exclusive prefix; all zero between levels
     uint64_t cap;
 };
 
@@ -290,6 +295,12 @@ __global__ void k_seed(Pool pool, Counters* ct, int level0, int src0, int n_wave
         pool.tau[2 * i + 1] = 0.0;
         if (want_child) pool.child[i] = kNoChild;
     }
+    // the sweeps count splitting rays per tile into zeroed counters, and every
+    // scatter clears the tiles it used
+    const uint64_t n_tiles = (pool.cap + kSplitTile - 1) / kSplitTile + 1;
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n_tiles;
+         t += (uint64_t)gridDim.x * blockDim.x)
+        pool.tsum[t] = 0u;
     (void)n_bins;
 }
 
@@ -888,6 +899,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             a.pool.tend[2 * slot] = is_split ? tau[0] : -1.0;
             a.pool.tend[2 * slot + 1] = (is_split && NB > 1) ? tau[NB - 1] : 0.0;
         }
+        // the claim's 64 rays lie in one tile of the child scan (tiles are whole
+        // multiples of a claim): add their splitting rays to its count
+        if (lane == 0 && nsplit) atomicAdd(&a.pool.tsum[li / (uint32_t)kSplitTile], nsplit);
 
         // ---- statistics: one atomic per counter per wavefront when the
         //      chunk belongs to a single source (the common case) ----
@@ -950,10 +964,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 // of the next level keeps every level in that order, so consecutive claims are
 // neighbouring directions of one source and the rays in flight at any moment
 // cover a small part of the grid (their gathers and deposits stay in cache).
-// Three passes per level: tiles of kSplitTile parents count their splitting
-// rays; one workgroup turns the counts into exclusive prefixes and sets the
-// next level's size; each tile then writes its children.
-constexpr int kSplitTile = 4096;
+// Per level: the sweep counts the splitting rays of each tile of kSplitTile
+// parents as its claims finish; one workgroup turns the counts into exclusive
+// prefixes and sets the next level's size; each tile then writes its children
+// and clears its count for the next level.
 constexpr int kSplitThreads = 256;
 
 // The level's rays [off, off + n); none after a pool overflow, when the tree is
@@ -963,31 +977,6 @@ __device__ inline void level_range(const Pool& pool, const Counters* ct, int lev
     const uint32_t t = ct->w.tail[level];
     n = (uint32_t)std::min<uint64_t>(t, pool.cap > off ? pool.cap - off : 0);
     if (ct->c.status & kStOverflow) n = 0;
-}
-
-__global__ void __launch_bounds__(kSplitThreads) k_split_count(Pool pool, const Counters* ct, int level) {
-    __shared__ uint32_t part[kSplitThreads / kWave];
-    uint64_t off;
-    uint32_t n;
-    level_range(pool, ct, level, off, n);
-    const uint32_t n_tiles = (n + kSplitTile - 1) / kSplitTile;
-    const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
-    for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        uint32_t cnt = 0;
-        for (uint32_t j = threadIdx.x; j < kSplitTile; j += kSplitThreads) {
-            const uint32_t i = t * kSplitTile + j;
-            if (i < n && pool.tend[2 * (off + i)] >= 0.0) ++cnt;
-        }
-        for (int o = kWave / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
-        if (lane == 0) part[w] = cnt;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t s = 0;
-            for (int k = 0; k < kSplitThreads / kWave; ++k) s += part[k];
-            pool.tsum[t] = s;
-        }
-        __syncthreads();
-    }
 }
 
 // One workgroup: exclusive prefix of the tile counts (in place); sets the
@@ -1074,6 +1063,7 @@ __global__ void __launch_bounds__(kSplitThreads) k_split_scatter(Pool pool, cons
             carry += all;
             __syncthreads();
         }
+        if (threadIdx.x == 0) pool.tsum[t] = 0u;  // read by every thread above, before the barriers
     }
 }
 
@@ -1688,11 +1678,10 @@ int seed_wave(art_ctx* c, int s0, int n_wave) {
 }
 
 // Sweep every level of the current wave, l0 first.
-// Children of level l, in parent order (see k_split_count).
+// Children of level l, in parent order (the sweep of level l counted them per tile).
 int split_level(art_ctx* c, int l) {
     const uint64_t tiles = (level_rays_bound(c, l) + kSplitTile - 1) / kSplitTile;
     const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(4096, tiles));
-    hipLaunchKernelGGL(k_split_count, dim3(blocks), dim3(kSplitThreads), 0, c->stream, c->pool, c->ct, l);
     hipLaunchKernelGGL(k_split_scan, dim3(1), dim3(1024), 0, c->stream, c->pool, c->ct, l);
     hipLaunchKernelGGL(k_split_scatter, dim3(blocks), dim3(kSplitThreads), 0, c->stream, c->pool, c->ct, l);
     HIP_TRY(hipGetLastError());
