@@ -101,6 +101,23 @@ struct SrcStats {
     unsigned long long* segments;
 };
 
+// Clears every per-source counter of a call in one launch.
+__global__ void k_zero_stats(SrcStats st, uint64_t ms) {
+    const uint64_t n_lev = ms * ART_MAX_LEVELS;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_lev;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        st.created[i] = 0u;
+        st.split[i] = 0u;
+        st.exited[i] = 0u;
+        st.term[i] = 0u;
+        if (i < 2 * ms) {
+            st.escaped[i] = 0.0;
+            st.residual[i] = 0.0;
+        }
+        if (i < ms) st.segments[i] = 0ull;
+    }
+}
+
 struct SweepArgs {
     Geo g;
     const float2* q;   // (n_H, x_n) per cell, packed once per call
@@ -1492,6 +1509,12 @@ int zero<uint32_t>(art_ctx* c, uint32_t* p, uint64_t n) {
     HIP_TRY(hipGetLastError());
     return ART_OK;
 }
+// The per-source counters of ms sources (levels, bins, segments).
+int zero_stats(art_ctx* c, uint64_t ms) {
+    hipLaunchKernelGGL(k_zero_stats, dim3(fill_blocks(ms * ART_MAX_LEVELS)), dim3(256), 0, c->stream, c->st, ms);
+    HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
 
 double r_max_host(double phi_c, int level) { return sqrt(3.0 / (M_PI * phi_c)) * ldexp(1.0, level); }
 
@@ -1865,11 +1888,7 @@ int art_trace(art_ctx* c, const float* n_H, const float* x_n, const double* src_
     } else if ((rc = zero(c, c->acc, (uint64_t)lpe * n_acc))) {
         return rc;
     }
-    if ((rc = zero(c, c->st.created, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.split, ms * ART_MAX_LEVELS)) ||
-        (rc = zero(c, c->st.exited, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.term, ms * ART_MAX_LEVELS)) ||
-        (rc = zero(c, c->st.escaped, ms * 2)) || (rc = zero(c, c->st.residual, ms * 2)) ||
-        (rc = zero(c, c->st.segments, ms)))
-        return rc;
+    if ((rc = zero_stats(c, ms))) return rc;
     const SweepArgs a = sweep_args(c, n_H, x_n, src_pos, src_lum, force, J, n_src);
     int waves = 0;
     for (int s0 = 0; s0 < n_src; s0 += c->wave_max) {
@@ -1949,11 +1968,7 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
         // rebuild the tree wave by wave (tau recomputed, no segment storage)
         if ((rc = begin_call(c, src_lum, n_src, n_H, x_n))) return rc;
         const uint64_t ms = (uint64_t)c->o.max_sources;
-        if ((rc = zero(c, c->st.created, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.split, ms * ART_MAX_LEVELS)) ||
-            (rc = zero(c, c->st.exited, ms * ART_MAX_LEVELS)) || (rc = zero(c, c->st.term, ms * ART_MAX_LEVELS)) ||
-            (rc = zero(c, c->st.escaped, ms * 2)) || (rc = zero(c, c->st.residual, ms * 2)) ||
-            (rc = zero(c, c->st.segments, ms)))
-            return rc;
+        if ((rc = zero_stats(c, ms))) return rc;
         const SweepArgs a = sweep_args(c, n_H, x_n, src_pos, src_lum, nullptr, nullptr, n_src);
         for (int s0 = 0; s0 < n_src; s0 += c->wave_max) {
             const int nw = std::min(c->wave_max, n_src - s0);
