@@ -643,6 +643,18 @@ int orc_adjoint(const orc_params *P, const double *nH, const double *xn, int n_s
 /* Small helpers exposed for the pin tests                                    */
 /* ------------------------------------------------------------------------- */
 
+/* The first n pixels of the level-l0 seed sequence in the order the stack pops
+ * them (Sec. 2.2, Step 1); returns how many were written. */
+int64_t orc_seed_order(int level0, int64_t *pix, int64_t n)
+{
+    orc_stack st = {0};
+    orc_seed(&st, level0, 1);
+    int64_t k = 0;
+    while (st.n && k < n) pix[k++] = st.r[--st.n].pix;
+    free(st.r);
+    return k;
+}
+
 /* Segments of a single ray from (xs, n) over [r_a, r_end] through a grid with
  * zero opacity: writes up to `cap` (cell, dr) pairs and returns the count
  * (or -count when truncated).  Used by the traversal pin test. */

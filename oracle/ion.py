@@ -44,27 +44,34 @@ def source_terms(n_H, x_n, Gamma, alpha_B: float):
     return I, R
 
 
-def substep_dt(n_H, x_n, Gamma, alpha_B: float, C: float) -> float:
+def substep_dt(n_H, x_n, Gamma, alpha_B: float, C: float, transparent=None) -> float:
     """dt_ss = C min(n_H / |I - R|) over cells with gas (Eq. e:dtss); +inf if no cell
-    changes."""
+    changes.  Cells flagged in ``transparent`` (sink control volumes, Sec. 4.1: the
+    radiation ignores their gas, whose state the subcycle leaves alone) set no
+    limit."""
     n_H = np.asarray(n_H, dtype=np.float64)
     I, R = source_terms(n_H, x_n, Gamma, alpha_B)
     d = np.abs(I - R)
     ok = (n_H > 0.0) & (d > 0.0)
+    if transparent is not None:
+        ok &= np.asarray(transparent).reshape(n_H.shape) == 0
     if not ok.any():
         return float("inf")
     return float(C) * float(np.min(n_H[ok] / d[ok]))
 
 
-def method_b(x0, n_H, Gamma, alpha_B: float, dt: float) -> np.ndarray:
+def method_b(x0, n_H, Gamma, alpha_B: float, dt: float, transparent=None) -> np.ndarray:
     """Eq. e:xn3: relaxation towards x_eq0 = alpha_B n_e / (Gamma + alpha_B n_e) on
-    the time scale t_ir = 1 / (Gamma + alpha_B n_e), with n_e = n_H (1 - x_0)."""
+    the time scale t_ir = 1 / (Gamma + alpha_B n_e), with n_e = n_H (1 - x_0).
+    Cells flagged in ``transparent`` (sink control volumes) keep x_0."""
     x0 = np.asarray(x0, dtype=np.float64)
     n_e = np.asarray(n_H, dtype=np.float64) * (1.0 - x0)
     a = float(alpha_B) * n_e
     s = np.asarray(Gamma, dtype=np.float64) + a
     out = x0.copy()
     m = s > 0.0
+    if transparent is not None:
+        m &= np.asarray(transparent).reshape(x0.shape) == 0
     x_eq = np.where(m, a / np.where(m, s, 1.0), 0.0)
     out[m] = x_eq[m] + (x0[m] - x_eq[m]) * np.exp(-float(dt) * s[m])
     return out
@@ -112,13 +119,16 @@ class SubcycleResult:
 
 
 def subcycle(nx, ny, nz, n_H, x_n, src_pos, src_lum, *, alpha_B, gamma_scale, C, t_end,
-             max_substeps=100000, trace_kw=None, on_substep=None) -> SubcycleResult:
+             max_substeps=100000, trace_kw=None, on_substep=None, transparent=None) -> SubcycleResult:
     """The radiation subcycle of one hydro step (Sec. 2.3 without hydro): repeat
     {FP64 sweep of the current x_n; Gamma = gamma_scale J_0; dt = min(dt_ss, t_end - t);
     x_n <- Method B; impulse += force dt} until t = t_end.  ``on_substep(k, t, x_n)``
-    is called after every substep."""
+    is called after every substep.  ``transparent``: sink control volumes, traced
+    without gas, with their x_n kept and no substep limit from them."""
     from oracle import oracle as O
     kw = dict(trace_kw or {})
+    if transparent is not None:
+        kw["transparent"] = transparent
     x = np.asarray(x_n, dtype=np.float64).reshape(-1).copy()
     nH = np.asarray(n_H, dtype=np.float64).reshape(-1)
     imp = np.zeros((3, x.size))
@@ -129,8 +139,8 @@ def subcycle(nx, ny, nz, n_H, x_n, src_pos, src_lum, *, alpha_B, gamma_scale, C,
             break
         res = O.trace(nx, ny, nz, nH, x, src_pos, src_lum, **kw)
         G = gamma_from_J(res.J[0], gamma_scale)
-        dt = min(substep_dt(nH, x, G, alpha_B, C), t_end - t)
-        x = method_b(x, nH, G, alpha_B, dt)
+        dt = min(substep_dt(nH, x, G, alpha_B, C, transparent), t_end - t)
+        x = method_b(x, nH, G, alpha_B, dt, transparent)
         imp += res.force * dt
         t = t + dt if t + dt < t_end else t_end
         dts.append(dt)

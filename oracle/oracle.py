@@ -10,6 +10,7 @@ fastest; ``force``/``v`` are ``[3, N]`` (structure of arrays).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -24,13 +25,23 @@ MAX_LEVELS = 16
 MAX_BINS = 2
 
 
+# gcc flags of the oracle: no FMA contraction, no fast math (the reference stays
+# plain FP64); the timing build adds -O3 -march=native, which leaves every
+# result bitwise unchanged under these flags
+CFLAGS = ["-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra"]
+
+
+def compile_library(src: str, out: str, opt=("-O2",)) -> str:
+    """gcc ``src`` into the shared library ``out`` with the oracle's flags."""
+    subprocess.check_call(["gcc", *opt, *CFLAGS, "-o", out + ".tmp", src, "-lm"])
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, no FMA contraction) into liboracle.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-Wextra", "-o", _LIB + ".tmp", _SRC, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
+        compile_library(_SRC, _LIB)
     return _LIB
 
 
@@ -53,31 +64,50 @@ class _Stats(C.Structure):
 _lib = None
 
 
+@contextlib.contextmanager
+def using_library(path: str):
+    """Run the wrappers below on another build of the oracle's source (a timing
+    build, or a test's deliberately altered copy), then restore the default."""
+    global _lib
+    keep = _lib
+    _lib = _bind(C.CDLL(path))
+    try:
+        yield
+    finally:
+        _lib = keep
+
+
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        lib = C.CDLL(_LIB)
-        P = C.POINTER(_Params)
-        d = C.POINTER(C.c_double)
-        lib.orc_trace.argtypes = [P, d, d, C.c_int, d, d, C.c_void_p, d, d, C.POINTER(_Stats)]
-        lib.orc_trace.restype = C.c_int
-        lib.orc_tangent.argtypes = [P, d, d, d, d, C.c_int, d, d, d, d]
-        lib.orc_tangent.restype = C.c_int
-        lib.orc_adjoint.argtypes = [P, d, d, C.c_int, d, d, d, d, d, d]
-        lib.orc_adjoint.restype = C.c_int
-        lib.orc_pix2vec_nest.argtypes = [C.c_int, C.c_int64, d]
-        lib.orc_pix2vec_nest.restype = None
-        lib.orc_pix2ang_nest.argtypes = [C.c_int, C.c_int64, d, d]
-        lib.orc_pix2ang_nest.restype = None
-        lib.orc_r_max.argtypes = [C.c_double, C.c_int]
-        lib.orc_r_max.restype = C.c_double
-        lib.orc_ray_segments.argtypes = [C.c_int, C.c_int, C.c_int, d, d, C.c_double,
-                                         C.c_double, C.POINTER(C.c_int64), d, C.c_int64]
-        lib.orc_ray_segments.restype = C.c_int64
-        _lib = lib
+        _lib = _bind(C.CDLL(_LIB))
     return _lib
+
+
+def _bind(lib):
+    """Declare the C signatures of the oracle's entry points on a loaded build."""
+    P = C.POINTER(_Params)
+    d = C.POINTER(C.c_double)
+    lib.orc_trace.argtypes = [P, d, d, C.c_int, d, d, C.c_void_p, d, d, C.POINTER(_Stats)]
+    lib.orc_trace.restype = C.c_int
+    lib.orc_tangent.argtypes = [P, d, d, d, d, C.c_int, d, d, d, d]
+    lib.orc_tangent.restype = C.c_int
+    lib.orc_adjoint.argtypes = [P, d, d, C.c_int, d, d, d, d, d, d]
+    lib.orc_adjoint.restype = C.c_int
+    lib.orc_pix2vec_nest.argtypes = [C.c_int, C.c_int64, d]
+    lib.orc_pix2vec_nest.restype = None
+    lib.orc_pix2ang_nest.argtypes = [C.c_int, C.c_int64, d, d]
+    lib.orc_pix2ang_nest.restype = None
+    lib.orc_r_max.argtypes = [C.c_double, C.c_int]
+    lib.orc_r_max.restype = C.c_double
+    lib.orc_ray_segments.argtypes = [C.c_int, C.c_int, C.c_int, d, d, C.c_double,
+                                     C.c_double, C.POINTER(C.c_int64), d, C.c_int64]
+    lib.orc_ray_segments.restype = C.c_int64
+    lib.orc_seed_order.argtypes = [C.c_int, C.POINTER(C.c_int64), C.c_int64]
+    lib.orc_seed_order.restype = C.c_int64
+    return lib
 
 
 def _dp(a: np.ndarray):
@@ -131,6 +161,13 @@ def pix2ang_nest(level: int, pix: int):
     return z.value, phi.value
 
 
+def seed_order(level0: int, n: int) -> np.ndarray:
+    """The first n level-l0 pixels in the order the oracle traces them (Sec. 2.2, Step 1)."""
+    out = np.zeros(n, dtype=np.int64)
+    k = _load().orc_seed_order(int(level0), out.ctypes.data_as(C.POINTER(C.c_int64)), int(n))
+    return out[:k]
+
+
 def r_max(phi_c: float, level: int) -> float:
     return _load().orc_r_max(float(phi_c), int(level))
 
@@ -149,7 +186,7 @@ def ray_segments(shape, xs, n, r_a, r_end, cap=100000):
 
 
 def _transparent(n_H, transparent):
-    """Sink control volumes (Sec. 4.1: radiation does not interact with the gas in
+    """Sink control volumes (Sec. 4.1: the radiation ignores the gas in
     them): the cells flagged in ``transparent`` neither absorb nor receive the
     absorbed photons, which is the sweep with no gas there."""
     nH = _f64(n_H).reshape(-1)

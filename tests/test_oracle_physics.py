@@ -177,6 +177,46 @@ def test_termination_threshold(oracle):
     assert lo <= res.residual[0, 0] <= hi
 
 
+def test_termination_every_bin(oracle):
+    """Two bins in a uniform medium with kappa_1 = kappa_0 / 4: a ray carries both
+    bins and is destroyed only once the optical depth exceeds tau_max in every bin
+    (the reading of Sec. 2.1's tau_max for several frequencies), so the
+    thinner bin 1 decides.  Each terminated ray then holds between
+    e^{-tau_max - kappa_1 sqrt(3)} and e^{-tau_max} of its bin-1 packet, and at most
+    e^{-4 tau_max} of its bin-0 packet.  Were a ray destroyed as soon as any one bin
+    passed tau_max, bin 1 would keep about e^{-tau_max / 4} per ray."""
+    n = 48
+    kappa0, kappa1, tmax = 0.8, 0.2, 4.0
+    wl = I.uniform_workload(n, [24.3, 23.8, 24.1], lum=1.0, s_H=kappa0 - kappa1, s_d=kappa1,
+                            n_bins=2, tau_term=tmax)
+    res = oracle.trace_workload(wl)
+    # every ray ends by optical depth: tau_1 reaches tau_max by r = tmax / kappa_1 + sqrt(3)
+    assert res.exited.sum() == 0 and res.terminated.sum() > 0
+    term = res.terminated[0]
+    lnom = np.array([1.0 / (12 * 4 ** lev) for lev in range(16)])
+    packets = float((term * lnom).sum())
+    lo = packets * math.exp(-tmax - kappa1 * math.sqrt(3))
+    hi = packets * math.exp(-tmax)
+    assert lo <= res.residual[0, 1] <= hi
+    assert res.residual[0, 0] <= packets * math.exp(-(kappa0 / kappa1) * tmax)
+    # photons are still conserved per bin
+    tot = res.absorbed + res.escaped + res.residual
+    assert np.allclose(tot, res.emitted[:, :2], rtol=1e-12, atol=0)
+
+
+def test_seed_order_step1(oracle):
+    """Sec. 2.2, Step 1: the level-l0 rays are injected base pixel by base pixel in
+    turn, pixel k of the sequence being (k mod 12) 4^l0 + k / 12; the paper prints
+    the start of that sequence for l0 = 4."""
+    g = golden("paper_values.json")["seed_order"]
+    first = g["first_14"]
+    got = oracle.seed_order(g["level0"], len(first))
+    assert list(got) == first
+    # and the whole sequence is a permutation of the level-l0 pixels
+    allp = oracle.seed_order(g["level0"], 12 * 4 ** g["level0"])
+    assert sorted(allp) == list(range(12 * 4 ** g["level0"]))
+
+
 # ---------------------------------------------------------------------------
 # Vacuum inverse-square law (Sec. 3.2, s:vacuum) and uniform-medium limit
 # ---------------------------------------------------------------------------

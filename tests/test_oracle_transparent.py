@@ -1,7 +1,7 @@
-"""Pins of the transparent sink control volumes (paper Sec. 4.1: radiation does not
-interact with the gas inside the control volume of a star particle) and of the
-force-only, non-ionizing mode of the M1 comparison (Sec. 4.3: ionizing radiation
-turned off, dust absorption only)."""
+"""Pins of the transparent sink control volumes (paper Sec. 4.1: the gas in a star
+particle's control volume neither absorbs nor feels the radiation) and of the
+force-only, non-ionizing mode of the M1 comparison (Sec. 4.3: no ionizing bin,
+dust absorption only)."""
 import math
 
 import numpy as np
@@ -134,3 +134,43 @@ def test_force_only_mode(oracle):
     d = np.stack([i.reshape(-1) - xs[0], j.reshape(-1) - xs[1], k.reshape(-1) - xs[2]])
     far = np.linalg.norm(d, axis=0) > 2.0
     assert np.all((d * res.force).sum(axis=0)[far] > 0.0)
+
+
+def test_subcycle_keeps_sink_cells(oracle):
+    """The ionization subcycle around sink control volumes (Sec. 4.1 with the
+    subcycle of Sec. 2.3): the flagged cells' gas takes no part, so their x_n is
+    never updated and they set no substep limit.  Checked on the oracle's pieces
+    against a cell-by-cell loop, and on a whole subcycle."""
+    from oracle import ion as X
+    p = I.rtype_problem(20)
+    wl = p.wl
+    rng = np.random.default_rng(7)
+    x0 = rng.uniform(0.05, 1.0, wl.n_cells)
+    mask = cube_mask(wl.nx, wl.src_pos[0], 2.5)
+    m = mask != 0
+    assert 0 < m.sum() < wl.n_cells
+    ref = oracle.trace(wl.nx, wl.ny, wl.nz, wl.n_H, x0, wl.src_pos, wl.src_lum, s_H=wl.s_H, s_d=0.0, n_bins=1,
+                       transparent=mask)
+    G = X.gamma_from_J(ref.J[0], p.gamma_scale)
+    # substep size: the minimum of n_H / |I - R| over the cells outside the mask
+    best = math.inf
+    for c in range(wl.n_cells):
+        if m[c]:
+            continue
+        n = float(wl.n_H[c])
+        ne = n * (1.0 - x0[c])
+        d = abs(G[c] * n * x0[c] - p.alpha_B * ne * ne)
+        if n > 0 and d > 0:
+            best = min(best, n / d)
+    dt = X.substep_dt(wl.n_H, x0, G, p.alpha_B, 0.1, transparent=mask)
+    assert dt == pytest.approx(0.1 * best, rel=1e-14)
+    assert dt > X.substep_dt(wl.n_H, x0, G, p.alpha_B, 0.1)  # the sink cells would limit it
+    x1 = X.method_b(x0, wl.n_H, G, p.alpha_B, dt, transparent=mask)
+    assert np.array_equal(x1[m], x0[m])
+    assert np.array_equal(x1[~m], X.method_b(x0, wl.n_H, G, p.alpha_B, dt)[~m])
+    res = X.subcycle(wl.nx, wl.ny, wl.nz, wl.n_H, x0, wl.src_pos, wl.src_lum, alpha_B=p.alpha_B,
+                     gamma_scale=p.gamma_scale, C=0.1, t_end=0.05, max_substeps=5,
+                     trace_kw=dict(s_H=wl.s_H, s_d=0.0, n_bins=1), transparent=mask)
+    assert len(res.dts) >= 2
+    assert np.array_equal(res.x_n[m], x0[m]) and not np.array_equal(res.x_n[~m], x0[~m])
+    assert np.all(res.impulse[:, m] == 0.0)
