@@ -13,9 +13,17 @@
  * The opacities are those of Sec. 2.3: chi_i = n_H (x_n sigma_H + sigma_d) for
  * the ionizing bin, chi_n = n_H sigma_d for the non-ionizing bin.
  *
- * Units: cell size dx = 1, cell volume 1, c = 1, h nu_i = 1.
- * Grid layout: cell (i, j, k) occupies [i,i+1) x [j,j+1) x [k,k+1); a field is a
- * flat array of nx*ny*nz values with x fastest: index (k*ny + j)*nx + i.
+ * Units and coordinates: lengths are in cells (dx = 1), measured from the
+ * domain's lower corner, which is the origin: the domain is
+ * [0,nx) x [0,ny) x [0,nz), cell (i, j, k) occupies [i,i+1) x [j,j+1) x [k,k+1),
+ * and source positions are given in these coordinates.  A caller with a
+ * physical cell size dx and origin x0 passes (x - x0) / dx and folds dx into the
+ * opacities: s_H = sigma_H dx and s_d = sigma_d dx are optical depths per cell
+ * length per unit density.  Cell volume 1, c = 1, h nu_i = 1.
+ * Field layout: a flat array of nx*ny*nz values with x fastest: index
+ * (k*ny + j)*nx + i.
+ * Frequency bins: bin 0 is ionizing (gas and dust opacity), bin 1 (if n_bins
+ * is 2) non-ionizing (dust only).
  *
  * Memory ownership: every pointer argument of art_trace / art_trace_adjoint is
  * DEVICE memory owned by the caller.  The library owns only its workspace (ray
@@ -48,8 +56,9 @@ extern "C" {
 #define ART_ERR_QUEUE_OVERFLOW (-4)   /* device: the ray pool filled up (no ray is dropped silently) */
 #define ART_ERR_SOURCE_OUTSIDE (-5)   /* device: a source position lies outside the domain */
 #define ART_ERR_DESTROY_COUNT (-6)    /* device: ended rays do not add up to N_src*12*4^level_max */
-#define ART_ERR_NO_FORWARD (-7)       /* adjoint requested on a context built without adjoint support */
+#define ART_ERR_NO_FORWARD (-7)       /* art_trace_adjoint_tape: no stored forward tree matches the call */
 #define ART_ERR_BAD_FIELD (-8)        /* device: a cell has n_H < 0 or not finite, or x_n outside [0, 1] */
+#define ART_ERR_NO_ADJOINT (-9)       /* adjoint requested on a context built without adjoint support */
 
 #define ART_DEPOSIT_ATOMIC 0          /* FP32 hardware atomics (fast, order-dependent rounding) */
 #define ART_DEPOSIT_DETERMINISTIC 1   /* 64-bit fixed-point integer sums: bitwise reproducible */
@@ -110,27 +119,64 @@ int art_set_stream(art_ctx *ctx, void *stream);
  *   x_n     [N]        neutral fraction per cell (float, in [0, 1])
  *   src_pos [n_src][3] source positions in cell units (double), inside [0,nx)x[0,ny)x[0,nz)
  *   src_lum [n_src][n_bins] source luminosity per bin (float, >= 0)
- *   rate    [N]        out: photoionizations per unit time, s_H x_n n_H J_0 (Eq. e:photrate2)
+ *   rate    [N]        out: photoionizations per unit time (Eq. e:photrate2): the
+ *                      gas's share x_n s_H / (x_n s_H + s_d) of the ionizing
+ *                      luminosity absorbed in the cell, i.e. s_H x_n n_H J_0
  *   force   [3][N]     out: absorbed momentum per unit time, sum over bins of
  *                      Delta L n (chi F / c, Eq. e:radforce), structure of arrays
  *   J       [n_bins][N] out (may be NULL): sum of L_in dr (1-e^{-dtau})/dtau per cell,
  *                      i.e. c E dV of Eq. e:Erad with the chi -> 0 limit taken
  * All sources share one ray pool; they are traced together in waves of as many
- * sources as the pool holds.  Asynchronous on the context's stream. */
+ * sources as the pool holds.  Asynchronous on the context's stream.
+ * On a context with adjoint support, a trace done in one wave keeps its ray tree
+ * in the pool as a tape for art_trace_adjoint_tape (see art_get_tape). */
 int art_trace(art_ctx *ctx, const float *n_H, const float *x_n, const double *src_pos,
               const float *src_lum, int n_src, float *rate, float *force, float *J);
 
+/* Token of the tape the last art_trace left (nonzero), or 0 if there is none: the
+ * context has no adjoint support, the trace needed several source waves, or a
+ * later call overwrote the pool or changed what the tree depends on
+ * (art_trace_adjoint, art_ion_substep, art_set_transparent, art_set_rotation,
+ * art_random_rotation, another art_trace).  Host-side only. */
+int art_get_tape(art_ctx *ctx, uint64_t *tape);
+
 /* Reverse-mode derivative of loss = sum_c g_rate[c] rate[c] + sum_c g_force[.][c] . force[.][c]
  * with respect to n_H and x_n, holding the ray tree of the forward sweep fixed
- * (the same splits, exits and optical-depth terminations).
+ * (the same splits, exits and optical-depth terminations; Sec. 2.1 splitting is
+ * geometric, so the tree changes only where a termination flips).
  *   g_rate [N], g_force [3][N]  in (device, float)
  *   g_nH [N], g_xn [N]          out (device, float), overwritten
- * Same n_H, x_n and sources as the forward sweep.  Requires enable_adjoint.
- * Recomputes the ray tree and every segment's optical depth instead of storing
- * segments, so it can run without a preceding art_trace. */
+ * n_H, x_n and the sources are those of the forward sweep to differentiate.
+ * Requires enable_adjoint (else ART_ERR_NO_ADJOINT).  Rebuilds the ray tree
+ * from these inputs, wave by wave (every segment's optical depth is recomputed,
+ * no segment is stored), so it needs no preceding art_trace and overwrites any
+ * stored tape. */
 int art_trace_adjoint(art_ctx *ctx, const float *n_H, const float *x_n, const double *src_pos,
                       const float *src_lum, int n_src, const float *g_rate,
                       const float *g_force, float *g_nH, float *g_xn);
+
+/* The same derivative over the tree a preceding art_trace stored, without
+ * tracing it again.  tape is the token art_get_tape returned after that trace,
+ * and n_H, x_n, src_pos, src_lum, n_src are the same pointers and count that
+ * trace was given; their contents must not have changed since (the library
+ * cannot check contents).  The tape stays valid, so several adjoints (other
+ * g_rate, g_force) may follow one trace.  ART_ERR_NO_FORWARD, with nothing
+ * enqueued, if the token is not that of the context's valid tape or the
+ * pointers differ from the trace's; otherwise as art_trace_adjoint. */
+int art_trace_adjoint_tape(art_ctx *ctx, uint64_t tape, const float *n_H, const float *x_n,
+                           const double *src_pos, const float *src_lum, int n_src,
+                           const float *g_rate, const float *g_force, float *g_nH, float *g_xn);
+
+/* art_trace and the adjoint of loss = <g_rate, rate> + <g_force, force> in one
+ * call, for callers that know the loss's weights when they trace (a loss that is
+ * linear in the outputs, or its linearisation at known weights).  Each source
+ * wave's tree is walked back right after that wave's forward sweep, so no tree
+ * is traced twice however many waves the sources need.  Arguments as art_trace
+ * and art_trace_adjoint (J may be NULL); requires enable_adjoint.  Leaves a tape
+ * (art_get_tape) when the sources fit one wave. */
+int art_trace_and_adjoint(art_ctx *ctx, const float *n_H, const float *x_n, const double *src_pos,
+                          const float *src_lum, int n_src, float *rate, float *force, float *J,
+                          const float *g_rate, const float *g_force, float *g_nH, float *g_xn);
 
 /* Synchronise the stream and return the device status of the last call. */
 int art_sync(art_ctx *ctx);
@@ -163,8 +209,8 @@ int art_get_timing(art_ctx *ctx, float *sweep_ms_total, int *sweep_launches, flo
 
 /* ---- Sink control volumes (Sec. 4.1) -------------------------------------------
  *
- * Radiation does not interact with the gas inside the control volume of a star
- * particle.  transparent is a device array of N bytes owned by the caller (nonzero =
+ * The gas in a star particle's control volume is invisible to the radiation: such
+ * cells are transparent.  transparent is a device array of N bytes owned by the caller (nonzero =
  * such a cell), or NULL for none; it stays in use until replaced, so it must stay
  * valid for every later call.  In flagged cells the gas neither absorbs nor receives
  * photons: no opacity, no rate, no force (J still holds the radiation passing

@@ -21,13 +21,15 @@ ART_ERR_SOURCE_OUTSIDE = -5
 ART_ERR_DESTROY_COUNT = -6
 ART_ERR_NO_FORWARD = -7
 ART_ERR_BAD_FIELD = -8
+ART_ERR_NO_ADJOINT = -9
 ART_DEPOSIT_ATOMIC = 0
 ART_DEPOSIT_DETERMINISTIC = 1
 ART_MAX_LEVELS = 16
 ART_MAX_BINS = 2
 
 # every symbol declared in include/art.h
-EXPORTED = ("art_create", "art_set_stream", "art_trace", "art_trace_adjoint", "art_sync",
+EXPORTED = ("art_create", "art_set_stream", "art_trace", "art_get_tape", "art_trace_adjoint",
+            "art_trace_adjoint_tape", "art_trace_and_adjoint", "art_sync",
             "art_get_stats", "art_autotune", "art_set_launch", "art_set_timing", "art_get_timing",
             "art_set_transparent", "art_set_rotation", "art_random_rotation", "art_get_rotation",
             "art_ion_substep", "art_ion_subcycle", "art_destroy", "art_strerror")
@@ -80,7 +82,10 @@ def lib() -> C.CDLL:
                                  C.POINTER(art_options), vp]
         L.art_set_stream.argtypes = [vp, vp]
         L.art_trace.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp]
+        L.art_get_tape.argtypes = [vp, C.POINTER(C.c_uint64)]
         L.art_trace_adjoint.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp, vp]
+        L.art_trace_adjoint_tape.argtypes = [vp, C.c_uint64, vp, vp, vp, vp, C.c_int, vp, vp, vp, vp]
+        L.art_trace_and_adjoint.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
         L.art_sync.argtypes = [vp]
         L.art_get_stats.argtypes = [vp, C.POINTER(art_stats), C.c_int, vp, vp, vp, vp, vp, vp, vp]
         L.art_autotune.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, C.POINTER(C.c_int),
@@ -140,6 +145,23 @@ def art_trace(ctx, n_H, x_n, src_pos, src_lum, n_src, rate, force, J):
 def art_trace_adjoint(ctx, n_H, x_n, src_pos, src_lum, n_src, g_rate, g_force, g_nH, g_xn):
     check(lib().art_trace_adjoint(C.c_void_p(ctx), n_H, x_n, src_pos, src_lum, int(n_src),
                                   g_rate, g_force, g_nH, g_xn), "art_trace_adjoint")
+
+
+def art_get_tape(ctx) -> int:
+    t = C.c_uint64()
+    check(lib().art_get_tape(C.c_void_p(ctx), C.byref(t)), "art_get_tape")
+    return t.value
+
+
+def art_trace_adjoint_tape(ctx, tape, n_H, x_n, src_pos, src_lum, n_src, g_rate, g_force, g_nH, g_xn):
+    check(lib().art_trace_adjoint_tape(C.c_void_p(ctx), C.c_uint64(int(tape)), n_H, x_n, src_pos, src_lum,
+                                       int(n_src), g_rate, g_force, g_nH, g_xn), "art_trace_adjoint_tape")
+
+
+def art_trace_and_adjoint(ctx, n_H, x_n, src_pos, src_lum, n_src, rate, force, J, g_rate, g_force,
+                          g_nH, g_xn):
+    check(lib().art_trace_and_adjoint(C.c_void_p(ctx), n_H, x_n, src_pos, src_lum, int(n_src), rate, force,
+                                      J, g_rate, g_force, g_nH, g_xn), "art_trace_and_adjoint")
 
 
 def art_sync(ctx) -> int:

@@ -88,6 +88,8 @@ class ArtTracer:
         o.pool_mem_fraction = float(pool_mem_fraction)
         o.block_size, o.blocks_per_cu = int(block_size), int(blocks_per_cu)
         self.params, self.options = p, o
+        self.last_tape = 0
+        self._tape_inputs = None
         with torch.cuda.device(self.device):
             self._ctx = A.art_create(nx, ny, nz, p, o, torch.cuda.current_stream().cuda_stream)
 
@@ -126,13 +128,18 @@ class ArtTracer:
         self._stream()
         A.art_trace(self._ctx, _ptr(n_H), _ptr(x_n), _ptr(src_pos), _ptr(src_lum), n_src,
                     _ptr(rate), _ptr(force), _ptr(J))
+        # token of the ray tree this trace left in the pool (0 if none): the inputs
+        # it was traced from are kept referenced with it, so that a later
+        # adjoint(..., tape=...) passes the very same device buffers
+        self.last_tape = A.art_get_tape(self._ctx)
+        self._tape_inputs = (n_H, x_n, src_pos, src_lum) if self.last_tape else None
         if check:
             A.check(A.art_sync(self._ctx), "art_trace (device)")
         return (rate, force, J) if want_J else (rate, force)
 
     # -- sink control volumes (Sec. 4.1) ----------------------------------------
     def set_transparent(self, mask):
-        """Flag cells where radiation does not interact with the gas (a uint8 or bool
+        """Flag transparent cells, whose gas the radiation ignores (a uint8 or bool
         device tensor of N cells, kept referenced here), or None to clear."""
         if mask is None:
             self._transparent = None
@@ -210,12 +217,22 @@ class ArtTracer:
                                   ip, float(t_end), int(max_substeps), _ptr(out[0]), _ptr(out[1]),
                                   _ptr(out[2]), _ptr(impulse))
 
-    def adjoint(self, n_H, x_n, src_pos, src_lum, g_rate, g_force, *, out=None, check=True):
-        """dL/dn_H, dL/dx_n for L = <g_rate, rate> + <g_force, force>."""
+    def adjoint(self, n_H, x_n, src_pos, src_lum, g_rate, g_force, *, tape=None, out=None, check=True):
+        """dL/dn_H, dL/dx_n for L = <g_rate, rate> + <g_force, force>.
+
+        Without ``tape`` the ray tree is traced again from the given inputs.  With
+        ``tape`` (the ``last_tape`` of a trace on this tracer, whose inputs must not
+        have changed since) the stored tree is reused; the inputs are those that
+        trace kept.  Raises ArtError (ART_ERR_NO_FORWARD) if that tape is gone."""
         d = self.device
-        n_H = _dev(n_H, torch.float32, d).reshape(-1)
-        x_n = _dev(x_n, torch.float32, d).reshape(-1)
-        src_pos = _dev(src_pos, torch.float64, d).reshape(-1, 3)
+        if tape:
+            if self._tape_inputs is None:
+                raise A.ArtError(A.ART_ERR_NO_FORWARD, "adjoint(tape=...)")
+            n_H, x_n, src_pos, src_lum = self._tape_inputs
+        else:
+            n_H = _dev(n_H, torch.float32, d).reshape(-1)
+            x_n = _dev(x_n, torch.float32, d).reshape(-1)
+            src_pos = _dev(src_pos, torch.float64, d).reshape(-1, 3)
         n_src = src_pos.shape[0]
         src_lum = _dev(src_lum, torch.float32, d).reshape(n_src, self.n_bins)
         g_rate = _dev(g_rate, torch.float32, d).reshape(-1)
@@ -226,11 +243,47 @@ class ArtTracer:
         else:
             g_nH, g_xn = out
         self._stream()
-        A.art_trace_adjoint(self._ctx, _ptr(n_H), _ptr(x_n), _ptr(src_pos), _ptr(src_lum), n_src,
-                            _ptr(g_rate), _ptr(g_force), _ptr(g_nH), _ptr(g_xn))
+        if tape:
+            A.art_trace_adjoint_tape(self._ctx, tape, _ptr(n_H), _ptr(x_n), _ptr(src_pos), _ptr(src_lum),
+                                     n_src, _ptr(g_rate), _ptr(g_force), _ptr(g_nH), _ptr(g_xn))
+        else:
+            A.art_trace_adjoint(self._ctx, _ptr(n_H), _ptr(x_n), _ptr(src_pos), _ptr(src_lum), n_src,
+                                _ptr(g_rate), _ptr(g_force), _ptr(g_nH), _ptr(g_xn))
         if check:
             A.check(A.art_sync(self._ctx), "art_trace_adjoint (device)")
         return g_nH, g_xn
+
+    def trace_and_adjoint(self, n_H, x_n, src_pos, src_lum, g_rate, g_force, *, want_J=False, out=None,
+                          check=True):
+        """Forward sweep and the adjoint of L = <g_rate, rate> + <g_force, force> in one
+        call (each source wave's tree is walked back right after it is traced).
+        Returns (rate, force[, J], g_nH, g_xn)."""
+        d = self.device
+        n_H = _dev(n_H, torch.float32, d).reshape(-1)
+        x_n = _dev(x_n, torch.float32, d).reshape(-1)
+        src_pos = _dev(src_pos, torch.float64, d).reshape(-1, 3)
+        n_src = src_pos.shape[0]
+        src_lum = _dev(src_lum, torch.float32, d).reshape(n_src, self.n_bins)
+        g_rate = _dev(g_rate, torch.float32, d).reshape(-1)
+        g_force = _dev(g_force, torch.float32, d).reshape(3, -1)
+        if n_H.numel() != self.N or x_n.numel() != self.N:
+            raise ValueError("field size does not match the grid")
+        if out is None:
+            out = (torch.empty(self.N, dtype=torch.float32, device=d),
+                   torch.empty((3, self.N), dtype=torch.float32, device=d),
+                   torch.empty((self.n_bins, self.N), dtype=torch.float32, device=d) if want_J else None,
+                   torch.empty(self.N, dtype=torch.float32, device=d),
+                   torch.empty(self.N, dtype=torch.float32, device=d))
+        rate, force, J, g_nH, g_xn = out
+        self._stream()
+        A.art_trace_and_adjoint(self._ctx, _ptr(n_H), _ptr(x_n), _ptr(src_pos), _ptr(src_lum), n_src,
+                                _ptr(rate), _ptr(force), _ptr(J), _ptr(g_rate), _ptr(g_force),
+                                _ptr(g_nH), _ptr(g_xn))
+        self.last_tape = A.art_get_tape(self._ctx)
+        self._tape_inputs = (n_H, x_n, src_pos, src_lum) if self.last_tape else None
+        if check:
+            A.check(A.art_sync(self._ctx), "art_trace_and_adjoint (device)")
+        return (rate, force, J, g_nH, g_xn) if want_J else (rate, force, g_nH, g_xn)
 
     def sync(self) -> int:
         return A.art_sync(self._ctx)
@@ -340,18 +393,22 @@ class ArtTrace(torch.autograd.Function):
     def forward(ctx, n_H, x_n, tracer: ArtTracer, src_pos, src_lum):
         rate, force = tracer.trace(n_H, x_n, src_pos, src_lum)
         ctx.tracer = tracer
+        ctx.tape = tracer.last_tape
         ctx.save_for_backward(n_H, x_n, src_pos, src_lum)
         return rate, force
 
     @staticmethod
     def backward(ctx, g_rate, g_force):
+        # autograd checks that the saved inputs were not modified in place, so the
+        # forward's tree may be reused as long as the tracer still holds it
         n_H, x_n, src_pos, src_lum = ctx.saved_tensors
         tr = ctx.tracer
         if g_rate is None:
             g_rate = torch.zeros(tr.N, dtype=torch.float32, device=n_H.device)
         if g_force is None:
             g_force = torch.zeros((3, tr.N), dtype=torch.float32, device=n_H.device)
-        g_nH, g_xn = tr.adjoint(n_H, x_n, src_pos, src_lum, g_rate, g_force)
+        tape = ctx.tape if ctx.tape and ctx.tape == A.art_get_tape(tr._ctx) else None
+        g_nH, g_xn = tr.adjoint(n_H, x_n, src_pos, src_lum, g_rate, g_force, tape=tape)
         return g_nH.view_as(n_H), g_xn.view_as(x_n), None, None, None
 
 

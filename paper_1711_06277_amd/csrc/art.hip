@@ -188,8 +188,8 @@ __global__ void k_fill_f64(double* p, uint64_t n) {
 }
 
 // Interleave (n_H, x_n) so that the sweep gathers one 8-byte word per segment.
-// transparent (optional): cells of sink control volumes, where radiation does not
-// interact with the gas (no gas as far as the sweep is concerned).
+// transparent (optional): cells of sink control volumes, whose gas the radiation
+// ignores (no gas as far as the sweep is concerned).
 // The fields are also checked here (the pass reads every cell anyway): a cell with
 // n_H < 0 or not finite, or x_n outside [0, 1], sets kStBadField.
 __global__ void k_pack(uint64_t N, const float* nH, const float* xn, const uint8_t* transparent, float2* q,
@@ -211,29 +211,50 @@ __global__ void k_pack_wv(uint64_t N, const float* w, const float* v, float4* wv
         wv[i] = make_float4(w[i], v[i], v[N + i], v[2 * N + i]);
 }
 
-// Reset the call counters and set the fixed-point scale of the deterministic
-// deposits (~2^50 / L_total, a power of two).
-__global__ void k_begin_call(Counters* ct, const float* src_lum, int n_lum) {
-    __shared__ double part[256];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n_lum; i += blockDim.x) s += fabs((double)src_lum[i]);
+// Reset the call counters and set the fixed-point scale of the deposits, a power
+// of two 2^k, as fine as two bounds allow:
+//   * one quantised value (a lane's deposit after the quad pre-combine) must
+//     stay below 2^50 so that fixed_point() converts it exactly.  A lane's value
+//     is at most sqrt(3) L_nom(l) summed over bins (a segment is at most a cell
+//     diagonal long, phi <= 1, the packet never grows), L_nom(l) <= L_s / (12 4^l0),
+//     and the combine adds at most the four lanes of a quad:
+//     D = 4 sqrt(3) max_s(sum_b L_s,b) / (12 4^l0);
+//   * a cell's sum must stay below 2^62: from one source, the rays of one level
+//     carry at most L_s in all and cross a cell once each (at most sqrt(3)), and a
+//     cell (radial extent sqrt(3)) meets at most n_shell levels' shells:
+//     S = n_shell sqrt(3) L_total.
+// Both get a margin of 2^-10 for the FP32 rounding of the values.
+__global__ void k_begin_call(Counters* ct, const float* src_lum, int n_src, int n_bins, int level0, int n_shell) {
+    __shared__ double part[256], pmax[256];
+    double s = 0.0, mx = 0.0;
+    for (int i = threadIdx.x; i < n_src; i += blockDim.x) {
+        double ls = 0.0;
+        for (int b = 0; b < n_bins; ++b) ls += fabs((double)src_lum[(uint64_t)i * n_bins + b]);
+        s += ls;
+        mx = fmax(mx, ls);
+    }
     part[threadIdx.x] = s;
+    pmax[threadIdx.x] = mx;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        if ((int)threadIdx.x < o) {
+            part[threadIdx.x] += part[threadIdx.x + o];
+            pmax[threadIdx.x] = fmax(pmax[threadIdx.x], pmax[threadIdx.x + o]);
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         const double L = part[0] > 0.0 ? part[0] : 1.0;
+        const double Lmax = pmax[0] > 0.0 ? pmax[0] : 1.0;
         ct->c.destroy = 0ull;
         ct->c.segments = 0ull;
         ct->c.rays_wave_max = 0ull;
         ct->c.status = 0u;
-        // a power of two, 2^49 / L <= scale < 2^50 / L: one deposit is at most
-        // L / 12 * sqrt(3) < L / 4 (a level-0 ray across a cell), so x * scale
-        // stays below 2^48 and converts with fixed_point(); a cell's sum stays
-        // below sqrt(3) L * scale < 2^51
-        int k = 50 - ilogb(L) - 1;
+        const double margin = 1.0 + 0x1p-10;
+        const double D = 4.0 * 1.7320508075688772 * Lmax / (12.0 * ldexp(1.0, 2 * level0)) * margin;
+        const double S = (double)n_shell * 1.7320508075688772 * L * margin;
+        // x < 2^(ilogb(x) + 1): D 2^(50 - ilogb(D) - 1) < 2^50, S 2^(62 - ilogb(S) - 1) < 2^62
+        int k = min(50 - ilogb(D) - 1, 62 - ilogb(S) - 1);
         k = k > 900 ? 900 : (k < -900 ? -900 : k);
         ct->c.scale = ldexp(1.0, k);
         ct->c.inv_scale = ldexp(1.0, -k);
@@ -684,9 +705,12 @@ struct GroupDeposit {
 // Forward sweep of one level
 // --------------------------------------------------------------------------
 
-// MODE 0: tree only (the tape pass of the adjoint); 1: J0 and the force;
-// 2: also J1 (the non-ionizing bin's J).  DET: a 64-bit fixed-point
-// accumulator, else FP32 (the LDS partial sums are fixed point in both).
+// MODE 0: tree only (the tape pass of the adjoint); 1: the rate and the force;
+// 2: also J of every bin.  DET: a 64-bit fixed-point accumulator, else FP32 (the
+// LDS partial sums are fixed point in both).  The rate is accumulated as what
+// Eq. e:photrate2 sums: the gas's share n_HI sigma_H / chi_i of the absorbed
+// ionizing luminosity of every segment, so a dense cell's rate is a sum of
+// values of the size of the absorbed packets (not a small J times a large n_H).
 // Quad pre-combine (DPP lane moves, no LDS): lanes 4k..4k+3 of a wavefront trace
 // the four children of one parent pixel and often cross the same cell in the same
 // step.  Partners lane^1 and then lane^2 compare keys; on a match the lower lane
@@ -726,9 +750,14 @@ __device__ __forceinline__ uint32_t claim_rays(uint32_t* head, int lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)base, 0) + (uint32_t)lane;
 }
 
-template <int MODE>
+// Values per cell and their places in the AoS accumulator (stride 4 or 8):
+// MODE 1: rate, F_x, F_y, F_z; MODE 2: J_0, F_x, F_y, F_z, rate[, J_1].
+template <int NB, int MODE>
 struct SweepVals {
-    static constexpr int NV = MODE == 2 ? 5 : 4;
+    static constexpr int NV = MODE == 2 ? 4 + NB : 4;
+    static constexpr int kRate = MODE == 2 ? 4 : 0;
+    static constexpr int kJ1 = 5;
+    static constexpr int LPE = NV <= 4 ? 4 : 8;
 };
 // Forward deposits, both modes: pairs of cells per slot, partial sums in 64-bit
 // fixed point in LDS (integer LDS atomics are fast, float ones are not), one
@@ -745,7 +774,8 @@ template <int NB, bool DET, int MODE>
 // Four wavefronts per SIMD (at most 128 VGPRs): the march is latency bound, and
 // the few registers this spills are outside the loop.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_sweep(SweepArgs a, int level) {
-    constexpr int NV = SweepVals<MODE>::NV;
+    using SV = SweepVals<NB, MODE>;
+    constexpr int NV = SV::NV;
     using Dep = SweepDeposit<NV>;
     using V = typename Dep::V;
     // Dynamic LDS: Dep::kBytes per wavefront of the workgroup (none in MODE 0)
@@ -818,15 +848,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         }
         // converged march: one segment per lane per iteration
         const float nxf = (float)r.n[0], nyf = (float)r.n[1], nzf = (float)r.n[2];
+        const float sHf = (float)g.s_H, sdf = (float)g.s_d;
         // The loop body twice per iteration: the march state then alternates
         // between two register sets instead of being copied back every step.
         auto step = [&]() __attribute__((always_inline)) {
+            // the current cell's (n_H, x_n), before march_step moves on
+            const float2 qv = m.q;
             if (MODE) {
                 // Flush what earlier steps staged, but only after this step's gather
                 // has arrived: the vector-memory counter retires in order, so the
                 // next step's wait for its gather also waits for these atomics, and
                 // issued here they have a whole step to complete.
-                const float2 qv = m.q;
                 __asm__ volatile("" ::"v"(qv.x), "v"(qv.y));
                 dep.flush(acc, lane, Dep::kFlushAt, inv_scale);
             }
@@ -851,22 +883,35 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                     if (seg) {
 #pragma clang fp contract(fast)
                         const float drf = (float)dr;
-                        float dLs = 0.0f, j0 = 0.0f, j1 = 0.0f;
+                        float dLs = 0.0f, dL0 = 0.0f, j0 = 0.0f, j1 = 0.0f;
 #pragma unroll
                         for (int b = 0; b < NB; ++b) {
                             const float x = (float)dtau[b];
                             const float Lin = lnom[b] * __expf(-(float)tin[b]);
                             float ph, om;
                             absorb_factors(x, ph, om);
-                            dLs += Lin * om;
-                            if (b == 0) j0 = Lin * drf * ph;
-                            else j1 = Lin * drf * ph;
+                            const float dL = Lin * om;
+                            dLs += dL;
+                            if (b == 0) dL0 = dL;
+                            if (MODE == 2) {
+                                if (b == 0) j0 = Lin * drf * ph;
+                                else j1 = Lin * drf * ph;
+                            }
                         }
-                        v[0] = j0;
+                        // the gas's share of the ionizing bin's absorption (Sec. 2.3
+                        // opacities): n_H x_n s_H / (n_H (x_n s_H + s_d)); zero where the
+                        // cell is empty or transparent (no absorption there)
+                        const float gas = qv.y * sHf;
+                        const float chi = gas + sdf;
+                        const float fgas = chi > 0.0f ? gas * __builtin_amdgcn_rcpf(chi) : 0.0f;
+                        v[SV::kRate] = fgas * dL0;
                         v[1] = nxf * dLs;
                         v[2] = nyf * dLs;
                         v[3] = nzf * dLs;
-                        if (NV > 4) v[4 % NV] = j1;
+                        if (MODE == 2) {
+                            v[0] = j0;
+                            if (NB > 1) v[SV::kJ1 % NV] = j1;
+                        }
                     }
                     // combined in FP32, then quantised: the pairs are fixed by the
                     // lane order, so fixed-point results stay reproducible
@@ -1092,32 +1137,34 @@ __global__ void k_end_wave(Counters* ct, int level0, int level_max) {
     atomicMax(&ct->c.rays_wave_max, tot);
 }
 
-// rate = s_H x_n n_H J_0 (Eq. e:photrate2); force and J from the AoS
-// accumulator (stride LPE), unpacking fixed point in deterministic mode.
+// rate (accumulated as the gas's share of the absorbed ionizing luminosity,
+// Eq. e:photrate2), force and J from the AoS accumulator (stride lpe: 4 without
+// J, 8 with J), unpacking fixed point in deterministic mode.  Transparent cells
+// get no rate or force (nothing is absorbed there).
 template <bool DET>
-__global__ void k_finalize(uint64_t N, const float* nH, const float* xn, const uint8_t* transparent, double s_H,
-                           const float* acc, const unsigned long long* det, int lpe, const Counters* ct, float* rate,
-                           float* force, float* J, int n_bins) {
+__global__ void k_finalize(uint64_t N, const uint8_t* transparent, const float* acc, const unsigned long long* det,
+                           int lpe, const Counters* ct, float* rate, float* force, float* J, int n_bins) {
     const double inv = DET ? ct->c.inv_scale : 0.0;
+    const int f_rate = lpe == 8 ? 4 : 0;
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N;
          c += (uint64_t)gridDim.x * blockDim.x) {
-        double v[5];
+        double v[6];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) {
-            if (f >= 4 && lpe < 8) {
+        for (int f = 0; f < 6; ++f) {
+            if (f >= 4 && (lpe < 8 || f >= 4 + n_bins)) {
                 v[f] = 0.0;
                 continue;
             }
             v[f] = DET ? (double)(long long)det[c * lpe + f] * inv : (double)acc[c * lpe + f];
         }
-        const double gas = (transparent && transparent[c]) ? 0.0 : (double)nH[c];
-        rate[c] = (float)(s_H * (double)xn[c] * gas * v[0]);
-        force[c] = (float)v[1];
-        force[N + c] = (float)v[2];
-        force[2 * N + c] = (float)v[3];
-        if (J) {
+        const bool sink = transparent && transparent[c];
+        rate[c] = sink ? 0.0f : (float)v[f_rate];
+        force[c] = sink ? 0.0f : (float)v[1];
+        force[N + c] = sink ? 0.0f : (float)v[2];
+        force[2 * N + c] = sink ? 0.0f : (float)v[3];
+        if (J && lpe == 8) {
             J[c] = (float)v[0];
-            if (n_bins > 1) J[N + c] = (float)v[4];
+            if (n_bins > 1) J[N + c] = (float)v[5];
         }
     }
 }
@@ -1288,6 +1335,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     dep.drain(acc, lane);
 }
 
+// Clear the adjoint's per-level claim counters (a reused tree is walked again).
+__global__ void k_adj_reset(Counters* ct) {
+    if (blockIdx.x == 0 && threadIdx.x <= ART_MAX_LEVELS) ct->w.adj_head[threadIdx.x] = 0u;
+}
+
 template <int NB, bool DET>
 size_t adjoint_lds_bytes(unsigned block) {
     return (size_t)(block / kWave) * AdjointDeposit<DET>::kBytes;
@@ -1452,10 +1504,14 @@ struct art_ctx {
     const uint8_t* transparent = nullptr;  // caller's per-cell sink flags, or none
     float2* q;                // [N] packed (n_H, x_n)
     float4* wv;               // [N] packed adjoint weights (w, v_x, v_y, v_z)
-    // tape of the last forward (valid only for a single-wave trace)
+    int n_shell;                // levels whose radial shells one cell can meet (fixed-point bound)
+    // tape of the last forward: its tree stays in the pool (single-wave traces only)
+    // until a later call overwrites the pool or changes what the tree depends on
     const void* tape_key[4];
     int tape_nsrc;
     bool tape_ok;
+    uint64_t tape_gen;          // token of the valid tape (0: none)
+    uint64_t gen;               // forward calls so far
     int last_nsrc, last_waves;
     // timing
     bool timing;
@@ -1551,6 +1607,18 @@ int deepest_level(int nx, int ny, int nz, const art_params& p) {
     return l;
 }
 
+// Levels whose radial shells [r_a(l), r_max(l)] a cell can meet: a cell spans at
+// most sqrt(3) in distance from a source, so it meets the two shells at the ends
+// of that range and every shell in between, each no wider than sqrt(3).
+int shells_per_cell(const art_params& p) {
+    int n = 2;
+    for (int l = p.level0; l < p.level_max; ++l) {
+        const double width = l == p.level0 ? r_max_host(p.phi_c, l) : r_max_host(p.phi_c, l - 1);
+        if (width <= sqrt(3.0)) ++n;
+    }
+    return n;
+}
+
 int check_params(const art_params* p) {
     if (!p) return ART_ERR_INVALID_ARG;
     if (p->level0 < 0 || p->level_max < p->level0 || p->level_max >= ART_MAX_LEVELS) return ART_ERR_INVALID_ARG;
@@ -1627,12 +1695,10 @@ SweepArgs sweep_args(art_ctx* c, const float* nH, const float* xn, const double*
     return a;
 }
 
-// mode 0: J0 only (adjoint tape pass); 1: J0 + force; 2: J0 + force + J1
-template <bool DET, int MODE>
+// mode 0: tree only (adjoint tape pass); 1: rate + force; 2: rate + force + J
+template <int NB, int MODE>
 size_t sweep_lds_bytes(unsigned block) {
-    return MODE ? (size_t)(block / kWave) *
-                      SweepDeposit<SweepVals<MODE>::NV>::kBytes
-                : 0;
+    return MODE ? (size_t)(block / kWave) * SweepDeposit<SweepVals<NB, MODE>::NV>::kBytes : 0;
 }
 
 // At most n_wave * 12 * 4^l rays exist at level l (and no more than the pool
@@ -1657,16 +1723,23 @@ int launch_sweep(art_ctx* c, const SweepArgs& a, int level, int mode) {
     const bool tm = c->timing && c->ev_used + 2 <= (int)c->ev.size();
     if (tm) HIP_TRY(hipEventRecord(c->ev[c->ev_used], c->stream));
 #define SWEEP(NB, DET, MODE)                                                                      \
-    hipLaunchKernelGGL((k_sweep<NB, DET, MODE>), grid, block, (sweep_lds_bytes<DET, MODE>(block.x)), c->stream, a, \
+    hipLaunchKernelGGL((k_sweep<NB, DET, MODE>), grid, block, (sweep_lds_bytes<NB, MODE>(block.x)), c->stream, a, \
                        level)
+#define SWEEP_MODES(NB, DET)                \
+    do {                                    \
+        if (mode == 2) SWEEP(NB, DET, 2);   \
+        else if (mode == 1) SWEEP(NB, DET, 1); \
+        else SWEEP(NB, DET, 0);             \
+    } while (0)
     if (nb == 1) {
-        if (det) { if (mode) SWEEP(1, true, 1); else SWEEP(1, true, 0); }
-        else { if (mode) SWEEP(1, false, 1); else SWEEP(1, false, 0); }
+        if (det) SWEEP_MODES(1, true);
+        else SWEEP_MODES(1, false);
     } else if (det) {
-        if (mode == 2) SWEEP(2, true, 2); else if (mode == 1) SWEEP(2, true, 1); else SWEEP(2, true, 0);
+        SWEEP_MODES(2, true);
     } else {
-        if (mode == 2) SWEEP(2, false, 2); else if (mode == 1) SWEEP(2, false, 1); else SWEEP(2, false, 0);
+        SWEEP_MODES(2, false);
     }
+#undef SWEEP_MODES
 #undef SWEEP
     HIP_TRY(hipGetLastError());
     if (tm) {
@@ -1723,7 +1796,8 @@ int sweep_wave(art_ctx* c, const SweepArgs& a, int mode) {
 }
 
 int begin_call(art_ctx* c, const float* lum, int n_src, const float* nH, const float* xn) {
-    hipLaunchKernelGGL(k_begin_call, dim3(1), dim3(256), 0, c->stream, c->ct, lum, n_src * c->p.n_bins);
+    hipLaunchKernelGGL(k_begin_call, dim3(1), dim3(256), 0, c->stream, c->ct, lum, n_src, c->p.n_bins, c->p.level0,
+                       c->n_shell);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_pack, dim3(fill_blocks(c->N)), dim3(256), 0, c->stream, c->N, nH, xn, c->transparent,
                        c->q, c->ct);
@@ -1744,7 +1818,8 @@ const char* art_strerror(int code) {
         case ART_ERR_QUEUE_OVERFLOW: return "ray pool overflow (increase pool_rays)";
         case ART_ERR_SOURCE_OUTSIDE: return "a source lies outside the domain";
         case ART_ERR_DESTROY_COUNT: return "destroy counter does not match N_src*12*4^level_max";
-        case ART_ERR_NO_FORWARD: return "context was created without adjoint support";
+        case ART_ERR_NO_FORWARD: return "no forward tape matches this adjoint call";
+        case ART_ERR_NO_ADJOINT: return "context was created without adjoint support";
         case ART_ERR_BAD_FIELD: return "a cell has n_H < 0 or not finite, or x_n outside [0, 1]";
         default: return "unknown error";
     }
@@ -1800,6 +1875,7 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
     // ray pool
     c->per_src_bound = rays_bound_per_source(nx, ny, nz, *params);
     c->deepest = deepest_level(nx, ny, nz, *params);
+    c->n_shell = shells_per_cell(*params);
     const uint64_t bytes_per_ray = 4 + 4 + 16 + 16 + (o.enable_adjoint ? 4 + 16 + 4 + 8 + 16 : 0);
     uint64_t cap = (uint64_t)o.pool_rays;
     if (cap == 0) {
@@ -1877,10 +1953,11 @@ int art_trace(art_ctx* c, const float* n_H, const float* x_n, const double* src_
     const uint64_t ms = (uint64_t)c->o.max_sources;
     c->ev_used = 0;
     c->tape_ok = false;
+    c->tape_gen = 0;
     if (c->timing) HIP_TRY(hipEventRecord(c->ev_call0, c->stream));
     int rc;
     if ((rc = begin_call(c, src_lum, n_src, n_H, x_n))) return rc;
-    const int mode = (J && c->p.n_bins > 1) ? 2 : 1;
+    const int mode = J ? 2 : 1;
     const int lpe = mode == 2 ? 8 : 4;
     const uint64_t n_acc = N + (N & 1);  // whole pairs
     if (det) {
@@ -1899,17 +1976,16 @@ int art_trace(art_ctx* c, const float* n_H, const float* x_n, const double* src_
     }
     const dim3 fg(fill_blocks(N)), fb(256);
     if (det)
-        hipLaunchKernelGGL((k_finalize<true>), fg, fb, 0, c->stream, N, n_H, x_n, c->transparent, c->p.s_H, c->acc,
-                           c->det, lpe,
-                           c->ct, rate, force, J, c->p.n_bins);
+        hipLaunchKernelGGL((k_finalize<true>), fg, fb, 0, c->stream, N, c->transparent, c->acc, c->det, lpe, c->ct,
+                           rate, force, J, c->p.n_bins);
     else
-        hipLaunchKernelGGL((k_finalize<false>), fg, fb, 0, c->stream, N, n_H, x_n, c->transparent, c->p.s_H, c->acc,
-                           c->det, lpe,
-                           c->ct, rate, force, J, c->p.n_bins);
+        hipLaunchKernelGGL((k_finalize<false>), fg, fb, 0, c->stream, N, c->transparent, c->acc, c->det, lpe, c->ct,
+                           rate, force, J, c->p.n_bins);
     HIP_TRY(hipGetLastError());
     if (c->timing) HIP_TRY(hipEventRecord(c->ev_call1, c->stream));
     c->last_nsrc = n_src;
     c->last_waves = waves;
+    c->gen += 1;
     if (c->o.enable_adjoint && waves == 1) {
         c->tape_key[0] = n_H;
         c->tape_key[1] = x_n;
@@ -1917,21 +1993,27 @@ int art_trace(art_ctx* c, const float* n_H, const float* x_n, const double* src_
         c->tape_key[3] = src_lum;
         c->tape_nsrc = n_src;
         c->tape_ok = true;
+        c->tape_gen = c->gen;
     }
     return ART_OK;
 }
 
-int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const double* src_pos, const float* src_lum,
-                      int n_src, const float* g_rate, const float* g_force, float* g_nH, float* g_xn) {
-    if (!c || !n_H || !x_n || !g_rate || !g_force || !g_nH || !g_xn) return ART_ERR_INVALID_ARG;
-    if (!c->o.enable_adjoint) return ART_ERR_NO_FORWARD;
-    if (n_src < 0 || n_src > c->o.max_sources) return ART_ERR_INVALID_ARG;
-    if (n_src > 0 && (!src_pos || !src_lum)) return ART_ERR_INVALID_ARG;
+int art_get_tape(art_ctx* c, uint64_t* tape) {
+    if (!c || !tape) return ART_ERR_INVALID_ARG;
+    *tape = c->tape_ok ? c->tape_gen : 0;
+    return ART_OK;
+}
+
+namespace {
+
+// The adjoint's fixed-point scales (from the weights and the largest density),
+// the cleared accumulator and the packed weights.  Then, after the levels'
+// reverse sweeps, finalize.
+int adjoint_prologue(art_ctx* c, const float* n_H, const float* src_lum, int n_src, const float* g_rate,
+                     const float* g_force) {
     const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
     const uint64_t N = c->N;
     int rc;
-    const bool reuse = c->tape_ok && c->tape_key[0] == n_H && c->tape_key[1] == x_n &&
-                       c->tape_key[2] == src_pos && c->tape_key[3] == src_lum && c->tape_nsrc == n_src;
     if (det) {
         if ((rc = zero(c, (uint32_t*)c->fscratch, 2))) return rc;
         hipLaunchKernelGGL(k_adj_scale, dim3(fill_blocks(N) < 1024 ? fill_blocks(N) : 1024), dim3(256), 0,
@@ -1944,11 +2026,12 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
     } else {
         if ((rc = zero(c, c->gk, 2 * N))) return rc;
     }
-    // the walk reads the packed fields; pack them again in case the tree is reused
-    hipLaunchKernelGGL(k_pack, dim3(fill_blocks(N)), dim3(256), 0, c->stream, N, n_H, x_n, c->transparent, c->q,
-                       c->ct);
     hipLaunchKernelGGL(k_pack_wv, dim3(fill_blocks(N)), dim3(256), 0, c->stream, N, g_rate, g_force, c->wv);
     HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+
+AdjArgs adjoint_args(art_ctx* c, const double* src_pos, const float* src_lum, int n_src) {
     AdjArgs aa;
     aa.g = c->geo;
     aa.q = c->q;
@@ -1959,35 +2042,142 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
     aa.ct = c->ct;
     aa.gk = c->gk;
     aa.gdet = c->gdet;
-    aa.N = (uint32_t)N;
+    aa.N = (uint32_t)c->N;
     aa.n_src = (uint32_t)n_src;
-    if (reuse) {
-        for (int l = c->deepest; l >= c->p.level0; --l)
-            if ((rc = launch_adjoint(c, aa, l))) return rc;
-    } else {
-        // rebuild the tree wave by wave (tau recomputed, no segment storage)
-        if ((rc = begin_call(c, src_lum, n_src, n_H, x_n))) return rc;
-        const uint64_t ms = (uint64_t)c->o.max_sources;
-        if ((rc = zero_stats(c, ms))) return rc;
-        const SweepArgs a = sweep_args(c, n_H, x_n, src_pos, src_lum, nullptr, nullptr, n_src);
-        for (int s0 = 0; s0 < n_src; s0 += c->wave_max) {
-            const int nw = std::min(c->wave_max, n_src - s0);
-            if ((rc = seed_wave(c, s0, nw))) return rc;
-            if ((rc = sweep_wave(c, a, 0))) return rc;
-            for (int l = c->deepest; l >= c->p.level0; --l)
-                if ((rc = launch_adjoint(c, aa, l))) return rc;
-        }
-        c->last_nsrc = n_src;
-        c->last_waves = (n_src + c->wave_max - 1) / c->wave_max;
+    return aa;
+}
+
+int adjoint_levels(art_ctx* c, const AdjArgs& aa) {
+    // the levels' claim counters start at zero for every walk over a tree
+    hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(64), 0, c->stream, c->ct);
+    HIP_TRY(hipGetLastError());
+    for (int l = c->deepest; l >= c->p.level0; --l) {
+        int rc = launch_adjoint(c, aa, l);
+        if (rc) return rc;
     }
+    return ART_OK;
+}
+
+int adjoint_epilogue(art_ctx* c, float* g_nH, float* g_xn) {
+    const uint64_t N = c->N;
     const dim3 fg(fill_blocks(N)), fb(256);
-    if (det)
+    if (c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC)
         hipLaunchKernelGGL((k_adj_finalize<true>), fg, fb, 0, c->stream, N, c->gk, c->gdet, c->ct, c->transparent,
                            g_nH, g_xn);
     else
         hipLaunchKernelGGL((k_adj_finalize<false>), fg, fb, 0, c->stream, N, c->gk, c->gdet, c->ct, c->transparent,
                            g_nH, g_xn);
     HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+
+int adjoint_check(art_ctx* c, const float* n_H, const float* x_n, const double* src_pos, const float* src_lum,
+                  int n_src, const float* g_rate, const float* g_force, float* g_nH, float* g_xn) {
+    if (!c || !n_H || !x_n || !g_rate || !g_force || !g_nH || !g_xn) return ART_ERR_INVALID_ARG;
+    if (!c->o.enable_adjoint) return ART_ERR_NO_ADJOINT;
+    if (n_src < 0 || n_src > c->o.max_sources) return ART_ERR_INVALID_ARG;
+    if (n_src > 0 && (!src_pos || !src_lum)) return ART_ERR_INVALID_ARG;
+    return ART_OK;
+}
+
+}  // namespace
+
+int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const double* src_pos, const float* src_lum,
+                      int n_src, const float* g_rate, const float* g_force, float* g_nH, float* g_xn) {
+    int rc = adjoint_check(c, n_H, x_n, src_pos, src_lum, n_src, g_rate, g_force, g_nH, g_xn);
+    if (rc) return rc;
+    // the pool is rebuilt here: no earlier tape survives
+    c->tape_ok = false;
+    c->tape_gen = 0;
+    if ((rc = adjoint_prologue(c, n_H, src_lum, n_src, g_rate, g_force))) return rc;
+    const AdjArgs aa = adjoint_args(c, src_pos, src_lum, n_src);
+    // rebuild the tree wave by wave (tau recomputed, no segment storage), and walk
+    // each wave's tree back before the next wave overwrites the pool
+    if ((rc = begin_call(c, src_lum, n_src, n_H, x_n))) return rc;
+    if ((rc = zero_stats(c, (uint64_t)c->o.max_sources))) return rc;
+    const SweepArgs a = sweep_args(c, n_H, x_n, src_pos, src_lum, nullptr, nullptr, n_src);
+    for (int s0 = 0; s0 < n_src; s0 += c->wave_max) {
+        const int nw = std::min(c->wave_max, n_src - s0);
+        if ((rc = seed_wave(c, s0, nw))) return rc;
+        if ((rc = sweep_wave(c, a, 0))) return rc;
+        if ((rc = adjoint_levels(c, aa))) return rc;
+    }
+    c->last_nsrc = n_src;
+    c->last_waves = (n_src + c->wave_max - 1) / c->wave_max;
+    return adjoint_epilogue(c, g_nH, g_xn);
+}
+
+int art_trace_adjoint_tape(art_ctx* c, uint64_t tape, const float* n_H, const float* x_n, const double* src_pos,
+                           const float* src_lum, int n_src, const float* g_rate, const float* g_force, float* g_nH,
+                           float* g_xn) {
+    int rc = adjoint_check(c, n_H, x_n, src_pos, src_lum, n_src, g_rate, g_force, g_nH, g_xn);
+    if (rc) return rc;
+    if (!(c->tape_ok && tape != 0 && tape == c->tape_gen && c->tape_key[0] == n_H && c->tape_key[1] == x_n &&
+          c->tape_key[2] == src_pos && c->tape_key[3] == src_lum && c->tape_nsrc == n_src))
+        return ART_ERR_NO_FORWARD;
+    // the packed fields and the tree are the forward's (nothing has run since)
+    if ((rc = adjoint_prologue(c, n_H, src_lum, n_src, g_rate, g_force))) return rc;
+    if ((rc = adjoint_levels(c, adjoint_args(c, src_pos, src_lum, n_src)))) return rc;
+    return adjoint_epilogue(c, g_nH, g_xn);
+}
+
+int art_trace_and_adjoint(art_ctx* c, const float* n_H, const float* x_n, const double* src_pos,
+                          const float* src_lum, int n_src, float* rate, float* force, float* J,
+                          const float* g_rate, const float* g_force, float* g_nH, float* g_xn) {
+    int rc = adjoint_check(c, n_H, x_n, src_pos, src_lum, n_src, g_rate, g_force, g_nH, g_xn);
+    if (rc) return rc;
+    if (!rate || !force) return ART_ERR_INVALID_ARG;
+    const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
+    const uint64_t N = c->N;
+    c->ev_used = 0;
+    c->tape_ok = false;
+    c->tape_gen = 0;
+    if (c->timing) HIP_TRY(hipEventRecord(c->ev_call0, c->stream));
+    if ((rc = begin_call(c, src_lum, n_src, n_H, x_n))) return rc;
+    const int mode = J ? 2 : 1;
+    const int lpe = mode == 2 ? 8 : 4;
+    const uint64_t n_acc = N + (N & 1);
+    if (det) {
+        if ((rc = zero(c, c->det, (uint64_t)lpe * n_acc))) return rc;
+    } else if ((rc = zero(c, c->acc, (uint64_t)lpe * n_acc))) {
+        return rc;
+    }
+    if ((rc = zero_stats(c, (uint64_t)c->o.max_sources))) return rc;
+    if ((rc = adjoint_prologue(c, n_H, src_lum, n_src, g_rate, g_force))) return rc;
+    const SweepArgs a = sweep_args(c, n_H, x_n, src_pos, src_lum, force, J, n_src);
+    const AdjArgs aa = adjoint_args(c, src_pos, src_lum, n_src);
+    // each wave's tree is walked back right after its forward sweep, while the
+    // pool still holds it: no wave is traced twice
+    int waves = 0;
+    for (int s0 = 0; s0 < n_src; s0 += c->wave_max) {
+        const int nw = std::min(c->wave_max, n_src - s0);
+        if ((rc = seed_wave(c, s0, nw))) return rc;
+        if ((rc = sweep_wave(c, a, mode))) return rc;
+        if ((rc = adjoint_levels(c, aa))) return rc;
+        ++waves;
+    }
+    const dim3 fg(fill_blocks(N)), fb(256);
+    if (det)
+        hipLaunchKernelGGL((k_finalize<true>), fg, fb, 0, c->stream, N, c->transparent, c->acc, c->det, lpe, c->ct,
+                           rate, force, J, c->p.n_bins);
+    else
+        hipLaunchKernelGGL((k_finalize<false>), fg, fb, 0, c->stream, N, c->transparent, c->acc, c->det, lpe, c->ct,
+                           rate, force, J, c->p.n_bins);
+    HIP_TRY(hipGetLastError());
+    if ((rc = adjoint_epilogue(c, g_nH, g_xn))) return rc;
+    if (c->timing) HIP_TRY(hipEventRecord(c->ev_call1, c->stream));
+    c->last_nsrc = n_src;
+    c->last_waves = waves;
+    c->gen += 1;
+    if (waves == 1) {  // the pool holds the whole tree: later adjoints may reuse it
+        c->tape_key[0] = n_H;
+        c->tape_key[1] = x_n;
+        c->tape_key[2] = src_pos;
+        c->tape_key[3] = src_lum;
+        c->tape_nsrc = n_src;
+        c->tape_ok = true;
+        c->tape_gen = c->gen;
+    }
     return ART_OK;
 }
 
@@ -2189,6 +2379,9 @@ int art_ion_substep(art_ctx* c, const float* n_H, float* x_n, const double* src_
                        (const uint8_t*)c->transparent, impulse, ip->gamma_scale, ip->alpha_B,
                        (const unsigned long long*)c->ion);
     HIP_TRY(hipGetLastError());
+    // x_n changed in place: the tree just traced no longer belongs to the inputs
+    c->tape_ok = false;
+    c->tape_gen = 0;
     return ART_OK;
 }
 

@@ -53,21 +53,38 @@ def compare_cells(name, gpu, ref, L_tot, rel=REL_TOL, floor=CELL_FLOOR):
     return float(err.max())
 
 
-def compare_force(gpu_F, ref_F, L_tot, kj_ref, rel=REL_TOL, floor=CELL_FLOOR):
-    """|dF| / |F| on cells with |F| above the floor.  FP32 rounding of the sum
-    scales with the summed magnitudes sum |Delta L n| <= sum_b kappa_b J_b, so
-    cells where opposite rays cancel (|F| << kappa J, e.g. around a source) are
-    held to rel * kappa J instead of rel * |F|."""
+# Cells whose net force is below this fraction of the summed magnitudes
+# sum_b kappa_b J_b >= sum |Delta L n| (rays from opposite sides cancel, e.g.
+# around a source): the FP32 rounding of each deposit, ~1e-7 relative, then sums
+# to ~1e-7 kappa J, which is 1e-4 of |F| only where |F| >= 1e-3 kappa J.
+CANCEL = 1e-3
+
+
+def compare_force(gpu_F, ref_F, L_tot, kj_ref, rel=REL_TOL, floor=CELL_FLOOR, name="force"):
+    """|dF| / |F| <= rel on every cell with |F| above the floor, except the
+    counted cancellation cells (|F| < CANCEL kappa J), which are held to
+    |dF| <= rel kappa J instead.  Returns (max |dF|/|F| over the other cells,
+    number of cancellation cells, max |dF| / (kappa J) over them)."""
     ref = np.asarray(ref_F, dtype=np.float64)
     gpu = np.asarray(gpu_F, dtype=np.float64)
+    kj = np.asarray(kj_ref, dtype=np.float64)
     fmag = np.linalg.norm(ref, axis=0)
     d = np.linalg.norm(gpu - ref, axis=0)
     m = fmag > floor * L_tot
-    scale = np.maximum(fmag, kj_ref)
-    err_rel = d[m] / fmag[m]
-    err = d[m] / scale[m]
-    assert err.max() <= rel, f"force: max err {err.max():.3e} (relative to max(|F|, kappa J))"
-    return float(err_rel.max()), float(err.max())
+    assert m.any(), f"{name}: no cell above threshold"
+    cancel = m & (fmag < CANCEL * kj)
+    plain = m & ~cancel
+    err_rel = d[plain] / fmag[plain]
+    err_c = d[cancel] / kj[cancel]
+    worst = float(err_rel.max(initial=0.0))
+    worst_c = float(err_c.max(initial=0.0))
+    print(f"\n{name}: {plain.sum()} cells at |dF|/|F| <= {worst:.2e}; {cancel.sum()} cancellation "
+          f"cells (|F| < {CANCEL:g} kappa J) at |dF|/(kappa J) <= {worst_c:.2e}")
+    assert worst <= rel, f"{name}: max |dF|/|F| {worst:.3e} over {plain.sum()} cells"
+    assert worst_c <= rel, f"{name}: max |dF|/(kappa J) {worst_c:.3e} over {cancel.sum()} cancellation cells"
+    # gpu cells below the floor stay tiny
+    assert d[~m].max(initial=0.0) <= 10 * floor * L_tot + 1e-30, f"{name}: spurious deposit"
+    return worst, int(cancel.sum()), worst_c
 
 
 def conservation(wl, J_gpu, st):

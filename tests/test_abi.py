@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 def test_error_strings():
     from paper_1711_06277_amd import _abi as A
     assert A.strerror(A.ART_OK) == "ok"
-    for code in range(-8, 0):
+    for code in range(-9, 0):
         assert A.strerror(code) != "unknown error"
     assert A.strerror(-99) == "unknown error"
 

@@ -30,9 +30,11 @@ def gpu_adjoint(wl, deterministic=False, with_forward=True, **opts):
         lum = torch.from_numpy(wl.src_lum).to(d)
         w = torch.from_numpy(wl.w).to(d)
         v = torch.from_numpy(wl.v).to(d)
+        tape = None
         if with_forward:
             tr.trace(nH, xn, pos, lum)
-        g_nH, g_xn = tr.adjoint(nH, xn, pos, lum, w, v)
+            tape = tr.last_tape or None
+        g_nH, g_xn = tr.adjoint(nH, xn, pos, lum, w, v, tape=tape)
         return g_nH.cpu().numpy(), g_xn.cpu().numpy()
     finally:
         tr.close()
@@ -128,3 +130,203 @@ def test_adjoint_through_opaque_cells(oracle, deterministic, n_dense, n_thick):
     assert np.isfinite(g_nH).all() and np.isfinite(g_xn).all()
     compare_grad("g_nH", g_nH, ref_nH)
     compare_grad("g_xn", g_xn, ref_xn)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def test_repeated_adjoints_over_one_tape(oracle):
+    """Several adjoints over the tree of one trace: the second with the same
+    weights is bitwise equal to the first (fixed point), and one with other
+    weights equals a fresh context's adjoint, which traces the tree again."""
+    import torch
+    from paper_1711_06277_amd.api import ArtTracer
+    wl = adjoint_problem(n=28, n_src=3, seed=9)
+    rng = np.random.default_rng(12)
+    w2 = rng.uniform(-1, 1, wl.n_cells).astype(np.float32)
+    v2 = rng.uniform(-1, 1, (3, wl.n_cells)).astype(np.float32)
+    kw = dict(s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins, tau_term=wl.tau_term, deterministic=True,
+              max_sources=wl.n_src, enable_adjoint=True)
+    args = (_dev(wl.n_H), _dev(wl.x_n), _dev(wl.src_pos), _dev(wl.src_lum))
+    tr = ArtTracer(wl.nx, wl.ny, wl.nz, **kw)
+    try:
+        tr.trace(*args)
+        tape = tr.last_tape
+        assert tape != 0
+        a1 = [t.clone() for t in tr.adjoint(*args, _dev(wl.w), _dev(wl.v), tape=tape)]
+        a2 = [t.clone() for t in tr.adjoint(*args, _dev(wl.w), _dev(wl.v), tape=tape)]
+        b1 = [t.clone() for t in tr.adjoint(*args, _dev(w2), _dev(v2), tape=tape)]
+        assert torch.any(a1[0] != 0)
+        for x, y in zip(a1, a2):
+            assert torch.equal(x, y)
+    finally:
+        tr.close()
+    fresh = ArtTracer(wl.nx, wl.ny, wl.nz, **kw)
+    try:
+        b2 = fresh.adjoint(*args, _dev(w2), _dev(v2))
+        for x, y in zip(b1, b2):
+            assert torch.equal(x, y)
+    finally:
+        fresh.close()
+    ref_nH, ref_xn = oracle.adjoint(wl.nx, wl.ny, wl.nz, wl.n_H, wl.x_n, wl.src_pos, wl.src_lum,
+                                    w2, v2, **wl.params())
+    compare_grad("g_nH", b1[0].cpu().numpy(), ref_nH)
+    compare_grad("g_xn", b1[1].cpu().numpy(), ref_xn)
+
+
+def test_tape_is_refused_when_stale():
+    """A tape token is refused (ART_ERR_NO_FORWARD) after any call that replaced
+    the stored tree or changed what it depends on, for other input pointers, and
+    is 0 for a trace split into several source waves."""
+    from paper_1711_06277_amd import _abi as A
+    from paper_1711_06277_amd.api import ArtTracer
+    wl = adjoint_problem(n=24, n_src=2)
+    args = (_dev(wl.n_H), _dev(wl.x_n), _dev(wl.src_pos), _dev(wl.src_lum))
+    w, v = _dev(wl.w), _dev(wl.v)
+    tr = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
+                   max_sources=wl.n_src, enable_adjoint=True)
+    try:
+        tr.trace(*args)
+        t1 = tr.last_tape
+        tr.trace(*args)
+        t2 = tr.last_tape
+        assert t1 and t2 and t1 != t2
+        with pytest.raises(A.ArtError) as e:  # an older trace's token
+            A.art_trace_adjoint_tape(tr._ctx, t1, *(A.C.c_void_p(t.data_ptr()) for t in args), wl.n_src,
+                                     A.C.c_void_p(w.data_ptr()), A.C.c_void_p(v.data_ptr()),
+                                     A.C.c_void_p(w.data_ptr()), A.C.c_void_p(v.data_ptr()))
+        assert e.value.code == A.ART_ERR_NO_FORWARD
+        other = args[0].clone()  # same contents, another buffer
+        with pytest.raises(A.ArtError) as e:
+            out = (torch_empty(wl.n_cells), torch_empty(wl.n_cells))
+            A.art_trace_adjoint_tape(tr._ctx, t2, A.C.c_void_p(other.data_ptr()),
+                                     *(A.C.c_void_p(t.data_ptr()) for t in args[1:]), wl.n_src,
+                                     A.C.c_void_p(w.data_ptr()), A.C.c_void_p(v.data_ptr()),
+                                     A.C.c_void_p(out[0].data_ptr()), A.C.c_void_p(out[1].data_ptr()))
+        assert e.value.code == A.ART_ERR_NO_FORWARD
+        tr.adjoint(*args, w, v, tape=t2)  # still valid
+        for invalidate in (lambda: tr.set_rotation(np.eye(3)), lambda: tr.set_transparent(None),
+                           lambda: tr.adjoint(*args, w, v)):
+            tr.trace(*args)
+            t = tr.last_tape
+            invalidate()
+            assert A.art_get_tape(tr._ctx) == 0
+            with pytest.raises(A.ArtError) as e:
+                tr.adjoint(*args, w, v, tape=t)
+            assert e.value.code == A.ART_ERR_NO_FORWARD
+    finally:
+        tr.close()
+    tm = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
+                   max_sources=wl.n_src, enable_adjoint=True, pool_rays=300000)
+    try:
+        tm.trace(*args)
+        assert tm.stats(wl.n_src).n_waves > 1 and tm.last_tape == 0
+    finally:
+        tm.close()
+    tn = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins, max_sources=wl.n_src)
+    try:
+        tn.trace(*args)
+        assert tn.last_tape == 0
+        with pytest.raises(A.ArtError) as e:
+            tn.adjoint(*args, w, v)
+        assert e.value.code == A.ART_ERR_NO_ADJOINT
+    finally:
+        tn.close()
+
+
+def torch_empty(n):
+    import torch
+    return torch.empty(n, dtype=torch.float32, device="cuda")
+
+
+def test_adjoint_after_ionization_substep(oracle):
+    """An ionization substep traces x_n and then updates it in place: the tree it
+    left belongs to the old x_n.  An adjoint afterwards on the same buffers traces
+    the updated x_n (the substep leaves no tape), and equals a fresh context's
+    adjoint (bitwise, fixed point) and the oracle adjoint of the updated x_n.
+    The R-type setup at 32^3 with the density lowered 200-fold (4.4 -> 2.2 optical
+    depths per cell length once ionized), so that the rays cross many cells and
+    the gradients are not the rounding noise of cells that absorb everything."""
+    import torch
+    from paper_1711_06277_amd.api import ArtTracer
+    p = I.rtype_problem(32)
+    wl = p.wl
+    wl.n_H = np.full(wl.n_cells, 0.005, dtype=np.float32)
+    w, v = I.random_adjoint_weights(wl.n_cells, seed=31)
+    nH, pos, lum = _dev(wl.n_H), _dev(wl.src_pos), _dev(wl.src_lum)
+    x = _dev(wl.x_n)
+    kw = dict(s_H=wl.s_H, s_d=wl.s_d, n_bins=1, max_sources=1, enable_adjoint=True, deterministic=True)
+    tr = ArtTracer(wl.nx, wl.ny, wl.nz, **kw)
+    try:
+        t_now = torch.zeros(1, dtype=torch.float64, device="cuda")
+        tr.ion_substep(nH, x, pos, lum, alpha_B=p.alpha_B, gamma_scale=p.gamma_scale, C=0.1, t_end=10.0,
+                       t_now=t_now)
+        from paper_1711_06277_amd import _abi as A
+        assert A.art_get_tape(tr._ctx) == 0
+        x_new = x.cpu().numpy()
+        assert not np.array_equal(x_new, wl.x_n)
+        g = [t.cpu().numpy() for t in tr.adjoint(nH, x, pos, lum, _dev(w), _dev(v))]
+    finally:
+        tr.close()
+    fresh = ArtTracer(wl.nx, wl.ny, wl.nz, **kw)
+    try:
+        gf = [t.cpu().numpy() for t in fresh.adjoint(nH, _dev(x_new), pos, lum, _dev(w), _dev(v))]
+    finally:
+        fresh.close()
+    ref_nH, ref_xn = oracle.adjoint(wl.nx, wl.ny, wl.nz, wl.n_H, x_new, wl.src_pos, wl.src_lum, w, v,
+                                    s_H=wl.s_H, s_d=wl.s_d, n_bins=1)
+    assert np.array_equal(g[0], gf[0]) and np.array_equal(g[1], gf[1])
+    compare_grad("g_nH", g[0], ref_nH)
+    compare_grad("g_xn", g[1], ref_xn)
+
+
+def test_adjoint_of_host_arrays_traces_their_contents(oracle):
+    """Host arrays are copied to temporary device buffers per call, which can land
+    on the addresses of an earlier call's temporaries: an adjoint of host arrays
+    whose contents differ from the preceding trace's is the adjoint of those
+    contents (the tree is traced again, never taken from the pool by address)."""
+    from paper_1711_06277_amd.api import ArtTracer
+    wl = adjoint_problem(n=24, n_src=2, seed=5)
+    x2 = np.clip(wl.x_n * np.float32(0.5), 0, 1).astype(np.float32)
+    tr = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
+                   max_sources=wl.n_src, enable_adjoint=True)
+    try:
+        tr.trace(wl.n_H, wl.x_n, wl.src_pos, wl.src_lum)
+        g_nH, g_xn = tr.adjoint(wl.n_H, x2, wl.src_pos, wl.src_lum, wl.w, wl.v)
+        g_nH, g_xn = g_nH.cpu().numpy(), g_xn.cpu().numpy()
+    finally:
+        tr.close()
+    ref_nH, ref_xn = oracle.adjoint(wl.nx, wl.ny, wl.nz, wl.n_H, x2, wl.src_pos, wl.src_lum,
+                                    wl.w, wl.v, **wl.params())
+    compare_grad("g_nH", g_nH, ref_nH)
+    compare_grad("g_xn", g_xn, ref_xn)
+
+
+def test_autograd_backward_twice(oracle):
+    """backward(retain_graph=True) twice over one forward gives the same gradient
+    twice (the stored tree is walked again with cleared claim counters)."""
+    import torch
+    from paper_1711_06277_amd.api import ArtTracer, art_trace
+    wl = adjoint_problem(n=24, n_src=2, seed=6)
+    tr = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
+                   max_sources=wl.n_src, enable_adjoint=True, deterministic=True)
+    try:
+        nH = _dev(wl.n_H).requires_grad_(True)
+        xn = _dev(wl.x_n).requires_grad_(True)
+        rate, force = art_trace(nH, xn, tr, _dev(wl.src_pos), _dev(wl.src_lum))
+        loss = (_dev(wl.w) * rate).sum() + (_dev(wl.v) * force).sum()
+        loss.backward(retain_graph=True)
+        g1 = (nH.grad.clone(), xn.grad.clone())
+        nH.grad = None
+        xn.grad = None
+        loss.backward()
+        assert torch.equal(nH.grad, g1[0]) and torch.equal(xn.grad, g1[1])
+        assert torch.any(g1[0] != 0)
+    finally:
+        tr.close()
+    ref_nH, ref_xn = oracle.adjoint(wl.nx, wl.ny, wl.nz, wl.n_H, wl.x_n, wl.src_pos, wl.src_lum,
+                                    wl.w, wl.v, **wl.params())
+    compare_grad("g_nH", g1[0].cpu().numpy(), ref_nH)
+    compare_grad("g_xn", g1[1].cpu().numpy(), ref_xn)

@@ -38,7 +38,9 @@ def test_graph_replay_matches_eager(deterministic, pool_rays):
 
         def step():
             tr.trace(nH, xn, pos, lum, out=(outs[0], outs[1], None), check=False)
-            tr.adjoint(nH, xn, pos, lum, w, v, out=(outs[2], outs[3]), check=False)
+            # over the stored tree when the trace kept one (one source wave)
+            tr.adjoint(nH, xn, pos, lum, w, v, tape=tr.last_tape or None, out=(outs[2], outs[3]),
+                       check=False)
 
         # eager reference
         step()

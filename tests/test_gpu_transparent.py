@@ -83,9 +83,8 @@ def test_transparent_cells_keep_their_ionization_state():
     ref = O.trace(wl.nx, wl.ny, wl.nz, wl.n_H, x0, wl.src_pos, wl.src_lum, s_H=wl.s_H, s_d=0.0, n_bins=1,
                   transparent=mask)
     G = X.gamma_from_J(ref.J[0], p.gamma_scale)
-    dt_ref = X.substep_dt(wl.n_H[~m], x0[~m], G[~m], p.alpha_B, 0.1)
-    x_ref = X.method_b(x0, wl.n_H, G, p.alpha_B, dt_ref)
-    x_ref[m] = x0[m]
+    dt_ref = X.substep_dt(wl.n_H, x0, G, p.alpha_B, 0.1, transparent=mask)
+    x_ref = X.method_b(x0, wl.n_H, G, p.alpha_B, dt_ref, transparent=mask)
     tr = tracer(wl)
     try:
         tr.set_transparent(dev(mask))
