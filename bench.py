@@ -4,8 +4,10 @@ A step is one full batched forward trace (seed, every level's sweep, finalize)
 of the 256^3 lognormal workload with 64 sources of log-uniform luminosity and
 two frequency bins, inputs resident in HBM.  Prints ONE JSON line with
 segments/s (whole job), ms per full trace per source, the plain (one source
-per call) comparison, the roofline of the sweep kernel and the FP64 oracle's
-rate on a bounded sample of the same workload.
+per call) comparison, the roofline of the sweep kernel, the adjoint, the
+ionization subcycle, the 512^3 / 1024-source forward + adjoint replayed from a
+HIP graph, and the FP64 oracle's rate on a bounded sample of the same workload
+(one core and all cores).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload 3]
 """
@@ -15,6 +17,7 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -22,8 +25,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+# Vector ALU issue of MI355X: 256 CUs x 4 SIMDs, each SIMD 16 lanes wide, so a
+# wave64 VALU instruction (FP32 or FP64, not packed) occupies a SIMD for 4 cycles:
+# one wave64 instruction per CU per cycle, 64 lane-operations, at 2.4 GHz.
+N_CU = 256
+CLOCK_HZ = 2.4e9
+VALU_PEAK_WAVE_INSTS = N_CU * CLOCK_HZ                  # wave64 VALU instructions / s
+VALU_PEAK_TOPS = VALU_PEAK_WAVE_INSTS * 64 / 1e12      # 39.3 T lane-operations / s
 # algorithmic bytes per ray-cell segment: the (n_H, x_n) gather (8 B) and a
-# read-modify-write of the cell's four FP32 outputs (J_i, F_x, F_y, F_z).  The
+# read-modify-write of the cell's four FP32 outputs (rate, F_x, F_y, F_z).  The
 # fixed-point mode's 8-byte accumulators would count 72 B; the roofline uses the
 # method's 40 B in both modes.
 BYTES_PER_SEGMENT = 40
@@ -79,11 +89,98 @@ def measured_traffic(workload: int, deterministic: bool):
     return _summary_value(name, "traffic_bytes_per_trace")
 
 
+def measured_valu(workload: int, deterministic: bool):
+    """VALU wave64 instructions per trace of the forward sweep (rocprofv3
+    SQ_INSTS_VALU summed over the sweep launches), or None if stale."""
+    if workload != 3:
+        return None
+    name = "k_sweep_c3_sq_counters.md" if deterministic else "k_sweep_c3_atomic_sq_counters.md"
+    return _summary_value(name, "valu_insts_per_trace")
+
+
 def measured_adjoint_traffic(workload: int, deterministic: bool):
     """HBM bytes per adjoint sweep, likewise (profiled in the fixed-point mode)."""
     if workload != 3 or not deterministic:
         return None
     return _summary_value("k_adjoint_c3_traffic.md", "traffic_bytes_per_adjoint")
+
+
+def measured_adjoint_valu(workload: int, deterministic: bool):
+    if workload != 3 or not deterministic:
+        return None
+    return _summary_value("k_adjoint_c3_sq_counters.md", "valu_insts_per_adjoint")
+
+
+def roofline(kernel_s, segments, bytes_per_segment, traffic_bytes, valu_insts, kernel, traffic_unit):
+    """The roofline block of a kernel: the method's bytes against HBM, the
+    measured HBM traffic, and the measured VALU issue against the chip's issue
+    rate.  The bound is whichever measured resource is busiest (HBM traffic or
+    VALU issue); its figures are the top-level achieved / peak / frac."""
+    model_gbs = segments * bytes_per_segment / kernel_s / 1e9
+    hbm = {"achieved": model_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": model_gbs / HBM_PEAK_GBS,
+           "bytes_per_segment": bytes_per_segment,
+           "measured_GBs": None if traffic_bytes is None else traffic_bytes / kernel_s / 1e9,
+           "measured_frac": None if traffic_bytes is None else traffic_bytes / kernel_s / 1e9 / HBM_PEAK_GBS}
+    valu = None
+    if valu_insts is not None:
+        tops = valu_insts * 64 / kernel_s / 1e12
+        valu = {"achieved": tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (VALU lane-operations)",
+                "frac": tops / VALU_PEAK_TOPS, "wave_insts_per_segment_x64": valu_insts * 64 / segments}
+    bound = "hbm"
+    if valu is not None and (hbm["measured_frac"] is None or valu["frac"] > hbm["measured_frac"]):
+        bound = "alu"
+    top = valu if bound == "alu" else hbm
+    return {"bound": bound, "achieved": top["achieved"], "peak": top["peak"],
+            "unit": "TOP/s" if bound == "alu" else "GB/s", "frac": top["frac"],
+            "traffic": None if traffic_bytes is None else traffic_bytes / 1e9, "traffic_unit": traffic_unit,
+            "kernel": kernel, "hbm_model": hbm, "valu_issue": valu}
+
+
+_BASELINE_WL = None  # the workload, inherited by the forked workers
+
+
+def _oracle_worker(args):
+    """One source of the bench workload through the oracle's timing build (a
+    worker process of the all-cores baseline)."""
+    lib, s = args
+    from oracle import oracle as O
+    with O.using_library(lib):
+        t = time.perf_counter()
+        ref = O.trace_workload(_BASELINE_WL.subset([s]))
+        return int(ref.segments.sum()), time.perf_counter() - t
+
+
+def cpu_baseline(wl):
+    """The FP64 oracle, as it stands, built -O3 -march=native (no FMA contraction,
+    no fast math: the same results), on the host's cores: one source on one core,
+    then one source per core on all the cores this process may use (at most 16).
+    Runs before anything touches the GPU (the workers are forked)."""
+    import multiprocessing as mp
+    from oracle import oracle as O
+    global _BASELINE_WL
+    _BASELINE_WL = wl
+    lib = os.path.join(ROOT, "oracle", "liboracle_timing.so")
+    O.compile_library(os.path.join(ROOT, "oracle", "art_oracle.c"), lib, opt=("-O3", "-march=native"))
+    seg1, dt1 = _oracle_worker((lib, 0))
+    log(f"[bench] oracle: {seg1 / dt1:.3e} segments/s on one core ({dt1:.1f} s)")
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(16, cores, wl.n_src))
+    t = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(lib, s) for s in range(cores)])
+    dt = time.perf_counter() - t
+    seg = sum(r[0] for r in res)
+    log(f"[bench] oracle: {seg / dt:.3e} segments/s on {cores} cores ({dt:.1f} s)")
+    return {"value": seg / dt, "unit": "segments/s", "cores": cores, "kind": "oracle",
+            "sample": f"sources 0..{cores - 1} of the {wl.n_src}-source {wl.nx}^3 workload, one per core "
+                      f"({seg} segments, {dt:.1f} s wall); oracle built -O3 -march=native -ffp-contract=off",
+            "ms_per_trace_per_source": 1e3 * dt / cores,
+            "single_core": {"value": seg1 / dt1, "unit": "segments/s", "cores": 1,
+                            "sample": f"source 0 ({seg1} segments, {dt1:.1f} s)",
+                            "ms_per_trace_per_source": 1e3 * dt1}}
 
 
 def main():
@@ -93,9 +190,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--no-plain", action="store_true", help="skip the one-source-per-call timing")
+    ap.add_argument("--plain-repeats", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint sweep timing")
     ap.add_argument("--no-ion", action="store_true", help="skip the ionization-subcycle timing")
+    ap.add_argument("--no-workload5", action="store_true",
+                    help="skip the 512^3 / 1024-source forward + adjoint graph step")
     ap.add_argument("--graph", action="store_true",
                     help="also time forward + adjoint captured in one HIP graph (adjoint leg)")
     ap.add_argument("--atomic", action="store_true",
@@ -113,15 +213,7 @@ def main():
               "sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
     from paper_1711_06277_amd import inputs as I
-    from paper_1711_06277_amd.api import ArtTracer
-
-    if not torch.cuda.is_available():
-        log("no GPU visible")
-        sys.exit(1)
-    dev = torch.device("cuda:0")
 
     t0 = time.time()
     wl = I.config(args.workload)
@@ -130,11 +222,25 @@ def main():
     wl.deterministic = not args.atomic
     log(f"[bench] workload {wl.name}: generated in {time.time() - t0:.1f}s")
 
-    tr = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
-                   level0=wl.level0, level_max=wl.level_max, phi_c=wl.phi_c,
-                   tau_term=wl.tau_term, deterministic=wl.deterministic,
-                   max_sources=wl.n_src, block_size=args.block_size,
-                   blocks_per_cu=args.blocks_per_cu, device=dev)
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
+    #      (first, while no GPU context exists in this process) ----
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
+
+    import torch
+    from paper_1711_06277_amd.api import ArtTracer
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+
+    def make_tracer(**kw):
+        return ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
+                         level0=wl.level0, level_max=wl.level_max, phi_c=wl.phi_c,
+                         tau_term=wl.tau_term, deterministic=wl.deterministic,
+                         block_size=args.block_size, blocks_per_cu=args.blocks_per_cu, device=dev, **kw)
+
+    tr = make_tracer(max_sources=wl.n_src)
     nH = torch.from_numpy(wl.n_H).to(dev)
     xn = torch.from_numpy(wl.x_n).to(dev)
     pos = torch.from_numpy(wl.src_pos).to(dev)
@@ -183,64 +289,73 @@ def main():
     log(f"[bench] batched: {ms_per_step:.2f} ms/trace, {seg_per_s:.3e} segments/s, "
         f"{ms_per_source:.3f} ms per trace per source")
 
-    # roofline of the sweep kernel: algorithmic bytes / summed kernel time
-    sweep_s = sweep_ms / 1e3
-    bps = BYTES_PER_SEGMENT
-    achieved_gbs = segments * args.steps * bps / sweep_s / 1e9
+    # roofline of the sweep kernel: measured per-launch durations (HIP events on
+    # the library's stream), summed over a trace
+    sweep_s = sweep_ms / 1e3 / args.steps
     avg_launch_ms = sweep_ms / max(1, sweep_launches)
+    roof = roofline(sweep_s, segments, BYTES_PER_SEGMENT, measured_traffic(args.workload, wl.deterministic),
+                    measured_valu(args.workload, wl.deterministic),
+                    "k_sweep (one launch per HEALPix level)",
+                    "GB per trace (sum over the per-level k_sweep launches), rocprofv3 FETCH_SIZE + "
+                    "WRITE_SIZE, copy-calibrated")
+    roof.update({"bytes_per_segment": BYTES_PER_SEGMENT,
+                 "bytes_per_segment_with_accumulator_width":
+                     BYTES_PER_SEGMENT_FIXED_POINT if wl.deterministic else BYTES_PER_SEGMENT,
+                 "sweep_ms_per_step": sweep_ms / args.steps, "avg_launch_ms": avg_launch_ms})
+    log(f"[bench] roofline: bound {roof['bound']}, frac {roof['frac']:.3f}; HBM model "
+        f"{roof['hbm_model']['frac']:.3f}")
 
     # ---- plain: one source per call, same kernel and parameters ----
     plain = None
     if not args.no_plain:
-        tp = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
-                       level0=wl.level0, level_max=wl.level_max, phi_c=wl.phi_c,
-                       tau_term=wl.tau_term, deterministic=wl.deterministic, max_sources=1,
-                       block_size=args.block_size, blocks_per_cu=args.blocks_per_cu, device=dev)
+        tp = make_tracer(max_sources=1)
         r1 = torch.empty_like(rate)
         f1 = torch.empty_like(force)
-        acc_r = torch.zeros_like(rate)
-        acc_f = torch.zeros_like(force)
-        tp.trace(nH, xn, pos[:1], lum[:1], out=(r1, f1, None), check=False)  # warm-up
-        torch.cuda.synchronize()
-        tp0 = time.perf_counter()
+        # untimed pass: the sum of the plain traces equals the batched trace
+        acc_r = torch.zeros(N, dtype=torch.float64, device=dev)
         for s in range(wl.n_src):
             tp.trace(nH, xn, pos[s:s + 1], lum[s:s + 1], out=(r1, f1, None), check=False)
             acc_r += r1
-            acc_f += f1
-        torch.cuda.synchronize()
-        t_plain = time.perf_counter() - tp0
+        m = rate.abs() > 1e-8 * float(wl.src_lum.sum())
+        rel = ((acc_r - rate.double()).abs()[m] / rate.double().abs()[m]).max().item() if m.any() else 0.0
+        del acc_r
+        times = []
+        for _ in range(args.plain_repeats):
+            torch.cuda.synchronize()
+            tp0 = time.perf_counter()
+            for s in range(wl.n_src):
+                tp.trace(nH, xn, pos[s:s + 1], lum[s:s + 1], out=(r1, f1, None), check=False)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - tp0)
         rc = tp.sync()
         tp.close()
-        # same accuracy: the sum of plain traces equals the batched trace
-        m = rate.abs() > 1e-8 * float(wl.src_lum.sum())
-        rel = ((acc_r - rate).abs()[m] / rate.abs()[m]).max().item() if m.any() else 0.0
-        plain = {"ms_per_trace": 1e3 * t_plain, "segments_per_s": segments / t_plain,
+        t_plain = statistics.median(times)
+        plain = {"ms_per_trace": 1e3 * t_plain, "ms_per_trace_min": 1e3 * min(times),
+                 "ms_per_trace_max": 1e3 * max(times), "repeats": len(times),
+                 "segments_per_s": segments / t_plain,
                  "ms_per_trace_per_source": 1e3 * t_plain / wl.n_src,
                  "speedup_batched_over_plain": t_plain / (t_total / args.steps),
                  "max_rel_diff_rate_vs_batched": rel, "status": rc}
-        log(f"[bench] plain: {1e3 * t_plain:.2f} ms for {wl.n_src} sources, speedup "
+        log(f"[bench] plain: median {1e3 * t_plain:.2f} ms for {wl.n_src} sources "
+            f"({1e3 * min(times):.2f}..{1e3 * max(times):.2f}), speedup "
             f"{plain['speedup_batched_over_plain']:.2f}x, max rel diff {rel:.2e}")
 
     # ---- adjoint: the forward trace records the tree, then the adjoint sweep
-    #      computes dL/dn_H and dL/dx_n for L = <w, rate> + <v, force> ----
+    #      walks it back for dL/dn_H and dL/dx_n, L = <w, rate> + <v, force> ----
     adjoint = None
     if not args.no_adjoint:
         tr.close()
         tr = None
-        ta = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
-                       level0=wl.level0, level_max=wl.level_max, phi_c=wl.phi_c,
-                       tau_term=wl.tau_term, deterministic=wl.deterministic,
-                       max_sources=wl.n_src, enable_adjoint=True, block_size=args.block_size,
-                       blocks_per_cu=args.blocks_per_cu, device=dev)
+        ta = make_tracer(max_sources=wl.n_src, enable_adjoint=True)
         w_np, v_np = I.random_adjoint_weights(N, seed=7000 + args.workload)
         w = torch.from_numpy(w_np).to(dev)
         v = torch.from_numpy(v_np).to(dev)
         g_nH = torch.empty(N, dtype=torch.float32, device=dev)
         g_xn = torch.empty(N, dtype=torch.float32, device=dev)
         ta.trace(nH, xn, pos, lum, out=out, check=False)
-        ta.adjoint(nH, xn, pos, lum, w, v, out=(g_nH, g_xn), check=False)
+        ta.adjoint(nH, xn, pos, lum, w, v, tape=ta.last_tape or None, out=(g_nH, g_xn), check=False)
         rc = ta.sync()
-        log("[bench] adjoint leg: warm-up done")
+        log(f"[bench] adjoint leg: warm-up done (tape {'kept' if ta.last_tape else 'not kept'})")
         t_fwd = t_adj = 0.0
         for _ in range(args.steps):
             torch.cuda.synchronize()
@@ -248,7 +363,7 @@ def main():
             ta.trace(nH, xn, pos, lum, out=out, check=False)
             torch.cuda.synchronize()
             ta1 = time.perf_counter()
-            ta.adjoint(nH, xn, pos, lum, w, v, out=(g_nH, g_xn), check=False)
+            ta.adjoint(nH, xn, pos, lum, w, v, tape=ta.last_tape or None, out=(g_nH, g_xn), check=False)
             torch.cuda.synchronize()
             ta2 = time.perf_counter()
             t_fwd += ta1 - ta0
@@ -262,7 +377,7 @@ def main():
 
             def fwd_adj():
                 ta.trace(nH, xn, pos, lum, out=out, check=False)
-                ta.adjoint(nH, xn, pos, lum, w, v, out=(g_nH, g_xn), check=False)
+                ta.adjoint(nH, xn, pos, lum, w, v, tape=ta.last_tape or None, out=(g_nH, g_xn), check=False)
 
             side = torch.cuda.Stream()
             side.wait_stream(torch.cuda.current_stream())
@@ -270,12 +385,10 @@ def main():
                 fwd_adj()
             torch.cuda.current_stream().wait_stream(side)
             torch.cuda.synchronize()
-            log("[bench] graph: warm-up on the capture stream done")
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
                 fwd_adj()
             torch.cuda.synchronize()
-            log("[bench] graph: captured")
             tg0 = time.perf_counter()
             for _ in range(args.steps):
                 g.replay()
@@ -288,20 +401,17 @@ def main():
             log(f"[bench] graph forward+adjoint: {1e3 * t_graph:.2f} ms per replay, equal to eager: {same}")
         ta.close()
         adj_s = t_adj / args.steps
-        adj_gbs = segments * ADJOINT_BYTES_PER_SEGMENT / adj_s / 1e9
-        adj_traffic = measured_adjoint_traffic(args.workload, wl.deterministic)
+        adj_roof = roofline(adj_s, segments, ADJOINT_BYTES_PER_SEGMENT,
+                            measured_adjoint_traffic(args.workload, wl.deterministic),
+                            measured_adjoint_valu(args.workload, wl.deterministic),
+                            "k_adjoint (one launch per level, deepest first; one backward walk over every segment)",
+                            "GB per adjoint sweep (sum over the per-level k_adjoint launches), rocprofv3 "
+                            "FETCH_SIZE + WRITE_SIZE, copy-calibrated")
+        adj_roof["bytes_per_segment"] = ADJOINT_BYTES_PER_SEGMENT
         adjoint = {"ms_per_adjoint": 1e3 * adj_s,
                    "ms_per_forward_with_tree": 1e3 * t_fwd / args.steps,
                    "segments_per_s": segments / adj_s,
-                   "status": rc, "gradients_finite": finite, "graph": graph,
-                   "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS,
-                                "unit": "GB/s", "frac": adj_gbs / HBM_PEAK_GBS,
-                                "traffic": None if adj_traffic is None else adj_traffic / 1e9,
-                                "traffic_unit": "GB per adjoint sweep (sum over the per-level k_adjoint "
-                                                "launches), rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated",
-                                "kernel": "k_adjoint (one launch per level, deepest first; "
-                                          "one backward walk over every segment)",
-                                "bytes_per_segment": ADJOINT_BYTES_PER_SEGMENT}}
+                   "status": rc, "gradients_finite": finite, "graph": graph, "roofline": adj_roof}
         log(f"[bench] adjoint: {1e3 * adj_s:.2f} ms per adjoint sweep "
             f"({segments / adj_s:.3e} segments/s), forward with tree "
             f"{1e3 * t_fwd / args.steps:.2f} ms, status {rc}")
@@ -332,7 +442,6 @@ def main():
         t_e = time.perf_counter() - te
         r_e = (3.0 * float((ix < 0.5).sum().item()) / (4.0 * math.pi)) ** (1.0 / 3.0)
         r_ref = p.R_S * (1.0 - math.exp(-4.0)) ** (1.0 / 3.0)
-        # graph of 8 substeps
         N1 = iw.n_cells
         iout = (torch.empty(N1, device=dev), torch.empty((3, N1), device=dev), torch.empty((1, N1), device=dev))
         t_now = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -376,6 +485,62 @@ def main():
             f"({1e3 * t_e / max(1, k_eager):.3f} ms/substep), graph {1e3 * t_g:.1f} ms for "
             f"{replays * chunk} substeps; front radius {r_e / r_ref - 1:+.4f} vs analytic")
 
+    if tr is not None:
+        tr.close()
+        tr = None
+
+    # ---- 512^3, 1024 sources (dN/dL ~ L^-2), fixed point: forward + adjoint of
+    #      L = <w, rate> + <v, force> in one call, captured in a HIP graph; one
+    #      eager step, then one replay, bitwise compared ----
+    w5 = None
+    if not args.no_workload5:
+        del nH, xn, pos, lum
+        t5 = time.time()
+        c5 = I.config(5)
+        log(f"[bench] workload {c5.name}: generated in {time.time() - t5:.1f}s")
+        tr5 = ArtTracer(c5.nx, c5.ny, c5.nz, s_H=c5.s_H, s_d=c5.s_d, n_bins=c5.n_bins, deterministic=True,
+                        max_sources=c5.n_src, enable_adjoint=True, device=dev)
+        a5 = [torch.from_numpy(x).to(dev) for x in (c5.n_H, c5.x_n, c5.src_pos, c5.src_lum, c5.w, c5.v)]
+        N5 = c5.n_cells
+        o5 = (torch.empty(N5, device=dev), torch.empty((3, N5), device=dev), None,
+              torch.empty(N5, device=dev), torch.empty(N5, device=dev))
+
+        def step5():
+            tr5.trace_and_adjoint(*a5, out=o5, check=False)
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        with torch.cuda.stream(side):
+            step5()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        t_eager5 = time.perf_counter() - te
+        rc5 = tr5.sync()
+        st5 = tr5.stats(c5.n_src)
+        ref5 = [o.clone() for o in o5 if o is not None]
+        log(f"[bench] workload 5 eager forward+adjoint: {t_eager5:.2f} s, {st5.segments} segments, "
+            f"{st5.n_waves} waves, status {rc5}")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step5()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        t_graph5 = time.perf_counter() - tg
+        same5 = all(torch.equal(a, b) for a, b in zip([o for o in o5 if o is not None], ref5))
+        rc5 = rc5 or tr5.sync()
+        del g
+        tr5.close()
+        w5 = {"workload": c5.name, "grid": [c5.nx, c5.ny, c5.nz], "n_sources": c5.n_src,
+              "segments_per_pass": st5.segments, "waves": st5.n_waves, "rays_max_wave": st5.rays_max_wave,
+              "s_forward_adjoint_eager": t_eager5, "s_forward_adjoint_graph_replay": t_graph5,
+              "segments_per_s_forward_plus_adjoint": 2 * st5.segments / t_graph5,
+              "graph_bitwise_equal_to_eager": same5, "status": rc5}
+        log(f"[bench] workload 5 graph forward+adjoint: {t_graph5:.2f} s per replay, equal to eager: {same5}")
+
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device=dev)
@@ -384,24 +549,6 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy probe: {args.copy_probe_mib} MiB read + written")
 
-    # ---- CPU baseline: the FP64 oracle on a bounded sample (one source) ----
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        sample = wl.subset([0])
-        tc = time.perf_counter()
-        ref = O.trace_workload(sample)
-        dt = time.perf_counter() - tc
-        seg_cpu = int(ref.segments.sum())
-        cpu = {"value": seg_cpu / dt, "unit": "segments/s", "cores": 1, "kind": "oracle",
-               "sample": f"source 0 of the {wl.n_src}-source {wl.nx}^3 workload "
-                         f"({seg_cpu} segments, {dt:.1f} s, single thread)",
-               "ms_per_trace_per_source": 1e3 * dt}
-        log(f"[bench] oracle: {seg_cpu / dt:.3e} segments/s on one core ({dt:.1f} s)")
-
-    if tr is not None:
-        tr.close()
-    traffic = measured_traffic(args.workload, wl.deterministic)
     result = {
         "metric": "ray-cell segments/s (batched, one full trace of all sources per step)",
         "value": seg_per_s,
@@ -425,17 +572,8 @@ def main():
         "plain": plain,
         "adjoint": adjoint,
         "ion_subcycle": ion,
-        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
-                     "traffic": None if traffic is None else traffic / 1e9,
-                     "traffic_unit": "GB per trace (sum over the per-level k_sweep launches), "
-                                     "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated",
-                     "kernel": "k_sweep (one launch per HEALPix level)",
-                     "bytes_per_segment": bps,
-                     "bytes_per_segment_with_accumulator_width":
-                         BYTES_PER_SEGMENT_FIXED_POINT if wl.deterministic else BYTES_PER_SEGMENT,
-                     "sweep_ms_per_step": sweep_ms / args.steps,
-                     "avg_launch_ms": avg_launch_ms},
+        "workload5_forward_adjoint_graph": w5,
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(result), flush=True)

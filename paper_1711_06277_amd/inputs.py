@@ -26,6 +26,7 @@ Seeds: workload ``c`` uses ``1000*c + {0: density, 1: second field,
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -33,14 +34,24 @@ import numpy as np
 TAU_TERM_1E10 = math.log(1.0e10)  # photon fraction 1e-10 -> tau = ln(1e10)
 
 
+def _fft_workers() -> int:
+    """Threads for the FFTs (pocketfft splits them into independent 1-D
+    transforms, so the result does not depend on the count)."""
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return 1
+
+
 def gaussian_field(n: int, std: float, seed: int) -> np.ndarray:
     """Periodic Gaussian random field on an n^3 grid, per-mode variance ~ |k|^-4.
 
     Returned as float64 with axes (z, y, x), mean 0 and the requested std.
     """
+    import scipy.fft as sfft
     rng = np.random.default_rng(seed)
     w = rng.standard_normal((n, n, n))
-    wk = np.fft.rfftn(w)
+    wk = sfft.rfftn(w, workers=_fft_workers())
     del w
     kz = np.fft.fftfreq(n) * n
     ky = np.fft.fftfreq(n) * n
@@ -51,7 +62,7 @@ def gaussian_field(n: int, std: float, seed: int) -> np.ndarray:
     amp[0, 0, 0] = 0.0
     wk *= amp
     del k2, amp
-    g = np.fft.irfftn(wk, s=(n, n, n), axes=(0, 1, 2))
+    g = sfft.irfftn(wk, s=(n, n, n), axes=(0, 1, 2), workers=_fft_workers())
     del wk
     g -= g.mean()
     g *= std / g.std()
@@ -77,7 +88,11 @@ def sample_sources(n_H: np.ndarray, n: int, n_src: int, rng: np.random.Generator
     """Cells drawn with probability ~ n_H (with replacement), centre + U(-0.25,0.25)^3."""
     p = n_H.astype(np.float64)
     p /= p.sum()
-    idx = rng.choice(p.size, size=n_src, replace=True, p=p)
+    # inverse-CDF draw, the same draws as rng.choice(p.size, n_src, p=p) without its
+    # slow validation of p
+    cdf = np.cumsum(p)
+    cdf /= cdf[-1]
+    idx = cdf.searchsorted(rng.random(n_src), side="right")
     i = idx % n
     j = (idx // n) % n
     k = idx // (n * n)
@@ -189,12 +204,10 @@ def config(c: int, n_src: int | None = None, n: int | None = None) -> Workload:
         pos = sample_sources(n_H, nn, ns, rng)
         li = 10.0 ** rng.uniform(0.0, 3.0, size=ns)
         lum = np.stack([li, 1.5 * li], axis=1).astype(np.float32)
-        rw = np.random.default_rng(4003)
-        w = rw.uniform(0.0, 1.0, size=nn ** 3).astype(np.float32)
-        v = rw.uniform(0.0, 1.0, size=(3, nn ** 3)).astype(np.float32)
+        w, v = random_adjoint_weights(nn ** 3, seed=4003)
         return Workload(name=f"c4: {nn}^3 lognormal, sigmoid x_n, {ns} sources, adjoint",
                         nx=nn, ny=nn, nz=nn, n_H=n_H, x_n=x_n, src_pos=pos, src_lum=lum,
-                        s_H=0.02, s_d=0.002, n_bins=2, w=w, v=np.ascontiguousarray(v))
+                        s_H=0.02, s_d=0.002, n_bins=2, w=w, v=v)
     if c == 5:
         nn = n or 512
         ns = n_src or 1024
@@ -204,14 +217,11 @@ def config(c: int, n_src: int | None = None, n: int | None = None) -> Workload:
         u = rng.uniform(0.0, 1.0, size=ns)
         li = 1.0 / (1.0 - u * (1.0 - 1.0e-4))
         lum = np.stack([li, 1.5 * li], axis=1).astype(np.float32)
-        rw = np.random.default_rng(5003)
-        w = rw.uniform(0.0, 1.0, size=nn ** 3).astype(np.float32)
-        v = rw.uniform(0.0, 1.0, size=(3, nn ** 3)).astype(np.float32)
+        w, v = random_adjoint_weights(nn ** 3, seed=5003)
         return Workload(name=f"c5: {nn}^3 lognormal std2, {ns} sources, 2 bins, deterministic",
                         nx=nn, ny=nn, nz=nn, n_H=n_H,
                         x_n=np.ones(nn ** 3, dtype=np.float32), src_pos=pos, src_lum=lum,
-                        s_H=0.02, s_d=0.002, n_bins=2, deterministic=True, w=w,
-                        v=np.ascontiguousarray(v))
+                        s_H=0.02, s_d=0.002, n_bins=2, deterministic=True, w=w, v=v)
     raise ValueError(f"unknown workload {c}")
 
 
@@ -224,10 +234,10 @@ Workload._renamed = _renamed  # type: ignore[attr-defined]
 
 
 def random_adjoint_weights(n_cells: int, seed: int):
-    """w ~ U[0,1] per cell and v ~ U[0,1]^3 per cell (SoA), float32."""
+    """w ~ U[0,1) per cell and v ~ U[0,1)^3 per cell (SoA), drawn as float32."""
     rw = np.random.default_rng(seed)
-    w = rw.uniform(0.0, 1.0, size=n_cells).astype(np.float32)
-    v = rw.uniform(0.0, 1.0, size=(3, n_cells)).astype(np.float32)
+    w = rw.random(n_cells, dtype=np.float32)
+    v = rw.random((3, n_cells), dtype=np.float32)
     return w, np.ascontiguousarray(v)
 
 

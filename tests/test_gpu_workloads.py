@@ -2,19 +2,25 @@
 benchmark uses (all sources of a workload in one batched call).
 
 The FP64 oracle cannot trace 64 sources at 256^3 (or 1024 at 512^3) in test
-time, so these tests compare what it can compute one by one (the ray tree and
-the escaped / residual luminosity of sampled sources) and properties that hold
-at any size: photon conservation, the destroy-counter total, linearity in the
-sources (batched == sum of one-source calls), and bitwise determinism.
+time, so these tests compare what it can compute one by one (the ray tree,
+escaped / residual luminosity and every cell of sampled sources), and
+properties that hold at any size: photon conservation, the destroy-counter
+total, linearity in the sources (batched == sum of calls over parts of the
+batch), and bitwise determinism.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
 
 from paper_1711_06277_amd import inputs as I
-from tests.gpu_common import CONS_TOL, compare_cells, conservation, kappas
+from tests.gpu_common import CONS_TOL, compare_cells, compare_force, conservation, kappas
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN5 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "workload5_sources.json")
 
 
 def tracer(wl, **kw):
@@ -28,15 +34,28 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
+@pytest.fixture(scope="module")
+def wl3():
+    return I.config(3)
+
+
+@pytest.fixture(scope="module")
+def refs3(wl3, oracle):
+    """The oracle's full trace (every cell) of sources 0 and 37 of workload 3."""
+    return {s: oracle.trace_workload(wl3.subset([s])) for s in (0, 37)}
+
+
 @pytest.mark.parametrize("deterministic", [True, False], ids=["fixed_point", "fp32_atomic"])
-def test_workload3_batched_full_size(oracle, deterministic):
+def test_workload3_batched_full_size(wl3, refs3, deterministic):
     """256^3, 64 sources, 2 bins, in both deposit modes (the benchmark times the
     fixed-point one): per-source trees of sampled sources match the oracle bit for
-    bit; batched equals the sum of one-source calls; photon conservation holds for
-    the whole batch; in fixed point a second call is bitwise equal."""
-    wl = I.config(3)
+    bit; one sampled source traced alone on the same context matches the oracle
+    in every cell; batched equals the sum of one-source calls; photon conservation
+    holds for the whole batch; in fixed point a second call is bitwise equal."""
+    wl = wl3
     tr = tracer(wl, max_sources=wl.n_src, deterministic=deterministic)
     nH, xn, pos, lum = dev(wl.n_H), dev(wl.x_n), dev(wl.src_pos), dev(wl.src_lum)
+    L = float(wl.src_lum.astype(np.float64).sum())
     try:
         rate, force, J = tr.trace(nH, xn, pos, lum, want_J=True)
         st = tr.stats(wl.n_src)
@@ -44,75 +63,135 @@ def test_workload3_batched_full_size(oracle, deterministic):
         assert st.destroy == st.destroy_expected == 64 * 12 * 4 ** 13
         cons = conservation(wl, J.cpu().numpy(), st)
         assert max(cons) <= CONS_TOL, cons
-        for s in (0, 37):
-            ref = oracle.trace_workload(wl.subset([s]))
+        for s, ref in refs3.items():
             for key, mine in (("created", st.src_created), ("split", st.src_split),
                               ("exited", st.src_exited), ("terminated", st.src_terminated)):
                 assert np.array_equal(mine[s], ref.__dict__[key][0]), (s, key)
-            np.testing.assert_allclose(st.src_escaped[s], ref.escaped[0], rtol=1e-5,
-                                       atol=1e-12 * float(lum.sum()))
-            np.testing.assert_allclose(st.src_residual[s], ref.residual[0], rtol=1e-4,
-                                       atol=1e-12 * float(lum.sum()))
+            np.testing.assert_allclose(st.src_escaped[s], ref.escaped[0], rtol=1e-5, atol=1e-12 * L)
+            np.testing.assert_allclose(st.src_residual[s], ref.residual[0], rtol=1e-4, atol=1e-12 * L)
             assert abs(int(st.src_segments[s]) / int(ref.segments[0]) - 1) < 1e-4
         rate_b, force_b = rate.clone(), force.clone()
         if deterministic:
             J_b = J.clone()
             rate2, force2, J2 = tr.trace(nH, xn, pos, lum, want_J=True)
             assert torch.equal(rate2, rate_b) and torch.equal(force2, force_b) and torch.equal(J2, J_b)
+        # one source alone on the benchmark's context, every cell against the oracle
+        ref = refs3[0]
+        Ls = float(wl.src_lum[0].astype(np.float64).sum())
+        r1, f1, J1 = (t.cpu().numpy() for t in tr.trace(nH, xn, pos[:1], lum[:1], want_J=True))
+        compare_cells("source 0 rate", r1, ref.rate, Ls)
+        for b in range(wl.n_bins):
+            compare_cells(f"source 0 J{b}", J1[b], ref.J[b], Ls)
+        kj = sum(k * j for k, j in zip(kappas(wl), ref.J))
+        compare_force(f1, ref.force, Ls, kj, name="source 0 force")
     finally:
         tr.close()
     tp = tracer(wl, max_sources=1, deterministic=deterministic)
     try:
-        acc_r = torch.zeros_like(rate_b)
-        acc_f = torch.zeros_like(force_b)
+        acc_r = torch.zeros_like(rate_b, dtype=torch.float64)
         for s in range(wl.n_src):
             r1, f1 = tp.trace(nH, xn, pos[s:s + 1], lum[s:s + 1])
             acc_r += r1
-            acc_f += f1
     finally:
         tp.close()
-    L = float(wl.src_lum.astype(np.float64).sum())
-    compare_cells("batched vs plain rate", rate_b.cpu().numpy(), acc_r.cpu().numpy().astype(np.float64), L)
+    compare_cells("batched vs plain rate", rate_b.cpu().numpy(), acc_r.cpu().numpy(), L)
 
 
-def test_workload4_adjoint_full_size(oracle):
-    """128^3, sigmoid x_n, 8 sources: GPU adjoint vs the FP64 oracle adjoint."""
+@pytest.mark.parametrize("deterministic", [False, True], ids=["fp64_accumulator", "fixed_point"])
+def test_workload4_adjoint_full_size(oracle, deterministic):
+    """128^3, sigmoid x_n, 8 sources: GPU adjoint (over the stored tree, as the
+    benchmark runs it) vs the FP64 oracle adjoint, in both accumulator modes."""
     wl = I.config(4)
     ref_nH, ref_xn = oracle.adjoint(wl.nx, wl.ny, wl.nz, wl.n_H, wl.x_n, wl.src_pos, wl.src_lum,
                                     wl.w, wl.v, **wl.params())
-    tr = tracer(wl, max_sources=wl.n_src, enable_adjoint=True)
+    tr = tracer(wl, max_sources=wl.n_src, enable_adjoint=True, deterministic=deterministic)
     try:
         args = (dev(wl.n_H), dev(wl.x_n), dev(wl.src_pos), dev(wl.src_lum))
         tr.trace(*args)
-        g_nH, g_xn = tr.adjoint(*args, dev(wl.w), dev(wl.v))
+        assert tr.last_tape
+        g_nH, g_xn = tr.adjoint(*args, dev(wl.w), dev(wl.v), tape=tr.last_tape)
     finally:
         tr.close()
     for name, gpu, ref in (("g_nH", g_nH, ref_nH), ("g_xn", g_xn, ref_xn)):
         gpu = gpu.cpu().numpy().astype(np.float64)
         m = np.abs(ref) > 1e-6 * np.abs(ref).max()
         err = np.abs(gpu[m] - ref[m]) / np.abs(ref[m])
+        print(f"\n{name}: max rel err {err.max():.2e} over {m.sum()} cells")
         assert err.max() <= 1e-4, f"{name}: {err.max():.3e}"
 
 
-def test_workload5_full_grid_deterministic_graph():
-    """512^3 std-2 field, a 32-source sample of the 1024 (dN/dL ~ L^-2), two bins,
-    deterministic deposits, forward + adjoint captured in one HIP graph: two
-    replays are bitwise equal, the destroy count is complete, photons are
-    conserved, and splitting the batch in two halves gives the same rate."""
-    full = I.config(5)
-    wl = full.subset(np.arange(0, 1024, 32))
+@pytest.fixture(scope="module")
+def wl5():
+    return I.config(5)
+
+
+def test_workload5_full_size_against_oracle(wl5):
+    """512^3 std-2 field, 1024 sources (dN/dL ~ L^-2), two bins, fixed-point
+    deposits, all sources in one call: the two sources the committed oracle file
+    holds (source 0 and the brightest) have the oracle's ray tree bit for bit and
+    its escaped / residual luminosity; and the batch equals the sum of 64 calls of
+    16 sources cell by cell (rate, J, |F|), which pins the fixed-point resolution
+    at this workload's luminosity range."""
+    wl = wl5
+    with open(GOLDEN5) as f:
+        gold = json.load(f)
+    nH, xn, pos, lum = dev(wl.n_H), dev(wl.x_n), dev(wl.src_pos), dev(wl.src_lum)
+    L = float(wl.src_lum.astype(np.float64).sum())
+    tr = tracer(wl, max_sources=wl.n_src, deterministic=True)
+    try:
+        rate, force, J = tr.trace(nH, xn, pos, lum, want_J=True)
+        st = tr.stats(wl.n_src)
+        print(f"\n{st.segments} segments in {st.n_waves} waves, rays in the largest wave {st.rays_max_wave}")
+        assert st.status == 0 and st.destroy == st.destroy_expected
+        cons = conservation(wl, J.cpu().numpy(), st)
+        assert max(cons) <= CONS_TOL, cons
+        for g in gold["sources"]:
+            s = g["index"]
+            assert np.allclose(wl.src_pos[s], g["pos"], rtol=0, atol=0)
+            for key, mine in (("created", st.src_created), ("split", st.src_split),
+                              ("exited", st.src_exited), ("terminated", st.src_terminated)):
+                assert np.array_equal(mine[s], np.array(g[key])), (s, key)
+            np.testing.assert_allclose(st.src_escaped[s], g["escaped"], rtol=1e-5, atol=1e-12 * L)
+            np.testing.assert_allclose(st.src_residual[s], g["residual"], rtol=1e-4, atol=1e-12 * L)
+            assert abs(int(st.src_segments[s]) / g["segments"] - 1) < 1e-4
+        rate_b = rate.cpu().numpy()
+        J_b = J.cpu().numpy()
+        F_b = force.cpu().numpy()
+        del rate, force, J
+        acc = torch.zeros((6, wl.n_cells), dtype=torch.float64, device="cuda")
+        for s0 in range(0, wl.n_src, 16):
+            r, f, j = tr.trace(nH, xn, pos[s0:s0 + 16], lum[s0:s0 + 16], want_J=True)
+            acc[0] += r
+            acc[1:4] += f
+            acc[4:6] += j
+        parts = acc.cpu().numpy()
+    finally:
+        tr.close()
+    compare_cells("rate: batch vs 64 parts", rate_b, parts[0], L)
+    for b in range(2):
+        compare_cells(f"J{b}: batch vs 64 parts", J_b[b], parts[4 + b], L)
+    kj = kappas(wl)[0] * parts[4] + kappas(wl)[1] * parts[5]
+    compare_force(F_b, parts[1:4], L, kj, name="force: batch vs 64 parts")
+
+
+def test_workload5_forward_adjoint_graph(wl5):
+    """The same workload's forward + adjoint (one call, each source wave walked
+    back after its sweep) captured in one HIP graph, on a 32-source sample of
+    the 1024: a replay is bitwise equal to the eager call, the destroy count is
+    complete, photons are conserved, and the gradient equals that of the
+    separate forward and adjoint calls."""
+    wl = wl5.subset(np.arange(0, 1024, 32))
     tr = tracer(wl, max_sources=wl.n_src, enable_adjoint=True, deterministic=True)
     nH, xn, pos, lum = dev(wl.n_H), dev(wl.x_n), dev(wl.src_pos), dev(wl.src_lum)
     w, v = dev(wl.w), dev(wl.v)
     N = wl.n_cells
     try:
-        outs = [torch.empty(N, device="cuda"), torch.empty((3, N), device="cuda"),
+        outs = (torch.empty(N, device="cuda"), torch.empty((3, N), device="cuda"),
                 torch.empty((2, N), device="cuda"), torch.empty(N, device="cuda"),
-                torch.empty(N, device="cuda")]
+                torch.empty(N, device="cuda"))
 
         def step():
-            tr.trace(nH, xn, pos, lum, want_J=True, out=(outs[0], outs[1], outs[2]), check=False)
-            tr.adjoint(nH, xn, pos, lum, w, v, out=(outs[3], outs[4]), check=False)
+            tr.trace_and_adjoint(nH, xn, pos, lum, w, v, want_J=True, out=outs, check=False)
 
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
@@ -121,30 +200,23 @@ def test_workload5_full_grid_deterministic_graph():
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         assert tr.sync() == 0
+        eager = [o.clone() for o in outs]
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             step()
-        g.replay()
-        torch.cuda.synchronize()
-        first = [o.clone() for o in outs]
+        for o in outs:
+            o.fill_(-1.0)
         g.replay()
         torch.cuda.synchronize()
         assert tr.sync() == 0
-        for a, b in zip(outs, first):
+        for a, b in zip(outs, eager):
             assert torch.equal(a, b)
         st = tr.stats(wl.n_src)
         assert st.destroy == st.destroy_expected
         cons = conservation(wl, outs[2].cpu().numpy(), st)
         assert max(cons) <= CONS_TOL, cons
-        assert torch.isfinite(outs[3]).all() and torch.isfinite(outs[4]).all()
-        rate_all = outs[0].clone()
-        half = wl.n_src // 2
-        r1, _ = tr.trace(nH, xn, pos[:half], lum[:half])
-        r1 = r1.clone()
-        r2, _ = tr.trace(nH, xn, pos[half:], lum[half:])
         del g
+        g_nH, g_xn = tr.adjoint(nH, xn, pos, lum, w, v)
+        assert torch.equal(g_nH, eager[3]) and torch.equal(g_xn, eager[4])
     finally:
         tr.close()
-    L = float(wl.src_lum.astype(np.float64).sum())
-    compare_cells("halves", (r1 + r2).cpu().numpy(), rate_all.cpu().numpy().astype(np.float64), L,
-                  rel=1e-5)
