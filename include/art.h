@@ -59,6 +59,7 @@ extern "C" {
 #define ART_ERR_NO_FORWARD (-7)       /* art_trace_adjoint_tape: no stored forward tree matches the call */
 #define ART_ERR_BAD_FIELD (-8)        /* device: a cell has n_H < 0 or not finite, or x_n outside [0, 1] */
 #define ART_ERR_NO_ADJOINT (-9)       /* adjoint requested on a context built without adjoint support */
+#define ART_ERR_TOO_LARGE (-10)       /* art_trace_noalloc: the input does not fit its static workspace */
 
 #define ART_DEPOSIT_ATOMIC 0          /* FP32 hardware atomics (fast, order-dependent rounding) */
 #define ART_DEPOSIT_DETERMINISTIC 1   /* 64-bit fixed-point integer sums: bitwise reproducible */
@@ -288,6 +289,34 @@ int art_ion_subcycle(art_ctx *ctx, const float *n_H, float *x_n, const double *s
 
 void art_destroy(art_ctx *ctx);
 const char *art_strerror(int code);
+
+/* ---- Forward sweep for callers that cannot allocate ------------------------------
+ *
+ * For code that may not call hipMalloc or create a context: under HIP graph
+ * capture, in tight serving loops, or in harnesses that forbid allocation.  The same
+ * forward sweep as art_trace (same kernels, same results: bitwise in the
+ * deterministic mode), with no context: the workspace (counters, per-source
+ * statistics, packed fields, accumulator, ray pool) lives in a static device array
+ * of ART_NOALLOC_SCRATCH_MIB MiB that the library holds on every GPU it runs on
+ * until the process ends.  Nothing is allocated or freed, by the library or by a
+ * library it calls.
+ *   nx, ny, nz, params       grid and method parameters as for art_create
+ *   n_H .. J                 as for art_trace (device memory owned by the caller)
+ *   status                   device int (may be NULL): after the call completes on
+ *                            the stream it holds ART_OK or the device-side error
+ *                            art_sync would report
+ *   stream                   hipStream_t the kernels are enqueued on (NULL = null stream)
+ * Sources are traced in waves that fit what is left of the array after the
+ * fixed parts (about 72 bytes per cell and 300 per source), at 40 bytes per ray.
+ * ART_ERR_TOO_LARGE, with nothing enqueued, if the fixed parts or one source's
+ * seed rays do not fit; a tree larger than the pool is reported as
+ * ART_ERR_QUEUE_OVERFLOW in *status.  Every call on a GPU uses that GPU's one
+ * array (it keeps the last call's contents; the call clears what it needs), so
+ * calls that overlap on one GPU, on different streams or threads, race. */
+#define ART_NOALLOC_SCRATCH_MIB 64
+int art_trace_noalloc(int nx, int ny, int nz, const art_params *params, const float *n_H,
+                      const float *x_n, const double *src_pos, const float *src_lum, int n_src,
+                      float *rate, float *force, float *J, int *status, void *stream);
 
 #ifdef __cplusplus
 }

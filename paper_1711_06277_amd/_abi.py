@@ -22,6 +22,8 @@ ART_ERR_DESTROY_COUNT = -6
 ART_ERR_NO_FORWARD = -7
 ART_ERR_BAD_FIELD = -8
 ART_ERR_NO_ADJOINT = -9
+ART_ERR_TOO_LARGE = -10
+ART_NOALLOC_SCRATCH_MIB = 64
 ART_DEPOSIT_ATOMIC = 0
 ART_DEPOSIT_DETERMINISTIC = 1
 ART_MAX_LEVELS = 16
@@ -32,7 +34,7 @@ EXPORTED = ("art_create", "art_set_stream", "art_trace", "art_get_tape", "art_tr
             "art_trace_adjoint_tape", "art_trace_and_adjoint", "art_sync",
             "art_get_stats", "art_autotune", "art_set_launch", "art_set_timing", "art_get_timing",
             "art_set_transparent", "art_set_rotation", "art_random_rotation", "art_get_rotation",
-            "art_ion_substep", "art_ion_subcycle", "art_destroy", "art_strerror")
+            "art_ion_substep", "art_ion_subcycle", "art_destroy", "art_strerror", "art_trace_noalloc")
 
 
 class art_params(C.Structure):
@@ -103,6 +105,8 @@ def lib() -> C.CDLL:
         L.art_ion_subcycle.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.POINTER(art_ion_params),
                                        C.c_double, C.c_int, vp, vp, vp, vp, C.POINTER(C.c_int),
                                        C.POINTER(C.c_double)]
+        L.art_trace_noalloc.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(art_params), vp, vp, vp, vp,
+                                        C.c_int, vp, vp, vp, vp, vp]
         L.art_destroy.argtypes = [vp]
         L.art_destroy.restype = None
         L.art_strerror.argtypes = [C.c_int]
@@ -230,6 +234,12 @@ def art_ion_subcycle(ctx, n_H, x_n, src_pos, src_lum, n_src, ip: art_ion_params,
                                  float(t_end), int(max_substeps), rate, force, J, impulse, C.byref(k),
                                  C.byref(t)), "art_ion_subcycle")
     return k.value, t.value
+
+
+def art_trace_noalloc(nx, ny, nz, params: art_params, n_H, x_n, src_pos, src_lum, n_src, rate, force, J,
+                      status, stream):
+    check(lib().art_trace_noalloc(int(nx), int(ny), int(nz), C.byref(params), n_H, x_n, src_pos, src_lum,
+                                  int(n_src), rate, force, J, status, C.c_void_p(stream)), "art_trace_noalloc")
 
 
 def art_destroy(ctx):

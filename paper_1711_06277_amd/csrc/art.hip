@@ -33,6 +33,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -1619,6 +1620,25 @@ int shells_per_cell(const art_params& p) {
     return n;
 }
 
+// Grid, method constants and the tree's size bounds of a context.
+void init_geometry(art_ctx* c, int nx, int ny, int nz, const art_params& p) {
+    Geo& g = c->geo;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.level0 = p.level0;
+    g.level_max = p.level_max;
+    g.n_bins = p.n_bins;
+    g.tau_term = p.tau_term;
+    g.s_H = p.s_H;
+    g.s_d = p.s_d;
+    g.rot = nullptr;  // set once the device copy exists
+    for (int l = 0; l < ART_MAX_LEVELS; ++l) g.rmax[l] = r_max_host(p.phi_c, l);
+    c->per_src_bound = rays_bound_per_source(nx, ny, nz, p);
+    c->deepest = deepest_level(nx, ny, nz, p);
+    c->n_shell = shells_per_cell(p);
+}
+
 int check_params(const art_params* p) {
     if (!p) return ART_ERR_INVALID_ARG;
     if (p->level0 < 0 || p->level_max < p->level0 || p->level_max >= ART_MAX_LEVELS) return ART_ERR_INVALID_ARG;
@@ -1820,6 +1840,7 @@ const char* art_strerror(int code) {
         case ART_ERR_DESTROY_COUNT: return "destroy counter does not match N_src*12*4^level_max";
         case ART_ERR_NO_FORWARD: return "no forward tape matches this adjoint call";
         case ART_ERR_NO_ADJOINT: return "context was created without adjoint support";
+        case ART_ERR_TOO_LARGE: return "grid and sources exceed the static workspace of art_trace_noalloc";
         case ART_ERR_BAD_FIELD: return "a cell has n_H < 0 or not finite, or x_n outside [0, 1]";
         default: return "unknown error";
     }
@@ -1859,23 +1880,7 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
         delete c;
         return ART_ERR_HIP;
     }
-    Geo& g = c->geo;
-    g.nx = nx;
-    g.ny = ny;
-    g.nz = nz;
-    g.level0 = params->level0;
-    g.level_max = params->level_max;
-    g.n_bins = params->n_bins;
-    g.tau_term = params->tau_term;
-    g.s_H = params->s_H;
-    g.s_d = params->s_d;
-    g.rot = nullptr;  // set once the device copy exists
-    for (int l = 0; l < ART_MAX_LEVELS; ++l) g.rmax[l] = r_max_host(params->phi_c, l);
-
-    // ray pool
-    c->per_src_bound = rays_bound_per_source(nx, ny, nz, *params);
-    c->deepest = deepest_level(nx, ny, nz, *params);
-    c->n_shell = shells_per_cell(*params);
+    init_geometry(c, nx, ny, nz, *params);
     const uint64_t bytes_per_ray = 4 + 4 + 16 + 16 + (o.enable_adjoint ? 4 + 16 + 4 + 8 + 16 : 0);
     uint64_t cap = (uint64_t)o.pool_rays;
     if (cap == 0) {
@@ -1943,11 +1948,12 @@ int art_set_stream(art_ctx* c, void* stream) {
     return ART_OK;
 }
 
-int art_trace(art_ctx* c, const float* n_H, const float* x_n, const double* src_pos, const float* src_lum,
-              int n_src, float* rate, float* force, float* J) {
-    if (!c || !n_H || !x_n || !rate || !force) return ART_ERR_INVALID_ARG;
-    if (n_src < 0 || n_src > c->o.max_sources) return ART_ERR_INVALID_ARG;
-    if (n_src > 0 && (!src_pos || !src_lum)) return ART_ERR_INVALID_ARG;
+namespace {
+
+// The forward sweep on a context whose workspace is in place (art_trace's body,
+// also run by art_trace_noalloc on its static workspace).
+int trace_impl(art_ctx* c, const float* n_H, const float* x_n, const double* src_pos, const float* src_lum,
+               int n_src, float* rate, float* force, float* J) {
     const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
     const uint64_t N = c->N;
     const uint64_t ms = (uint64_t)c->o.max_sources;
@@ -1996,6 +2002,16 @@ int art_trace(art_ctx* c, const float* n_H, const float* x_n, const double* src_
         c->tape_gen = c->gen;
     }
     return ART_OK;
+}
+
+}  // namespace
+
+int art_trace(art_ctx* c, const float* n_H, const float* x_n, const double* src_pos, const float* src_lum,
+              int n_src, float* rate, float* force, float* J) {
+    if (!c || !n_H || !x_n || !rate || !force) return ART_ERR_INVALID_ARG;
+    if (n_src < 0 || n_src > c->o.max_sources) return ART_ERR_INVALID_ARG;
+    if (n_src > 0 && (!src_pos || !src_lum)) return ART_ERR_INVALID_ARG;
+    return trace_impl(c, n_H, x_n, src_pos, src_lum, n_src, rate, force, J);
 }
 
 int art_get_tape(art_ctx* c, uint64_t* tape) {
@@ -2415,3 +2431,140 @@ void art_destroy(art_ctx* c) {
 }
 
 }  // extern "C"
+
+// --------------------------------------------------------------------------
+// Forward sweep without any allocation (art_trace_noalloc)
+// --------------------------------------------------------------------------
+
+// The workspace of art_trace_noalloc: one array per GPU, held until the process
+// ends.  In host code `scratch` names a host-side stand-in, not the device
+// array: kernels and copies get the address hipGetSymbolAddress returns for the
+// current device.
+constexpr size_t kScratchBytes = (size_t)ART_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices];
+
+// The device address of `scratch` on the current device, looked up once per device.
+int scratch_on_device(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return ART_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ART_ERR_HIP;
+        g_scratch[dev] = (unsigned char*)p;
+    }
+    *out = g_scratch[dev];
+    return ART_OK;
+}
+
+// Carves the workspace of one call out of [base, base + kScratchBytes): counters,
+// per-source statistics, the rotation, the packed fields, the accumulator and,
+// in what is left, the ray pool.  Returns false if the fixed parts or the seeds
+// of one source do not fit.
+struct Carver {
+    unsigned char* base;
+    size_t used = 0;
+    template <class T>
+    T* take(uint64_t n) {
+        used = (used + 255) & ~(size_t)255;
+        T* p = (T*)(base + used);
+        used += (size_t)n * sizeof(T);
+        return p;
+    }
+};
+
+bool noalloc_layout(art_ctx* c, unsigned char* base, int n_src, bool want_J) {
+    Carver cv{base};
+    const uint64_t N = c->N;
+    const uint64_t ms = (uint64_t)std::max(1, n_src);
+    c->ct = cv.take<Counters>(1);
+    c->st.created = cv.take<uint32_t>(ms * ART_MAX_LEVELS);
+    c->st.split = cv.take<uint32_t>(ms * ART_MAX_LEVELS);
+    c->st.exited = cv.take<uint32_t>(ms * ART_MAX_LEVELS);
+    c->st.term = cv.take<uint32_t>(ms * ART_MAX_LEVELS);
+    c->st.escaped = cv.take<double>(ms * 2);
+    c->st.residual = cv.take<double>(ms * 2);
+    c->st.segments = cv.take<unsigned long long>(ms);
+    c->rot = cv.take<double>(9);
+    c->q = cv.take<float2>(N);
+    const uint64_t n_acc = (uint64_t)(want_J ? 8 : 4) * (N + (N & 1));
+    if (c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC) c->det = cv.take<unsigned long long>(n_acc);
+    else c->acc = cv.take<float>(n_acc);
+    if (cv.used + 4096 > kScratchBytes) return false;
+    // the pool: 40 bytes per ray plus a tile count per kSplitTile rays, and padding
+    const uint64_t room = kScratchBytes - cv.used - 5 * 256;
+    uint64_t cap = (room - 8) / (40 + 1);
+    cap = std::min<uint64_t>(cap, 0xfffffff0ull);
+    c->pool.tsum = cv.take<uint32_t>((cap + kSplitTile - 1) / kSplitTile + 1);
+    c->pool.tau = cv.take<double>(2 * cap);
+    c->pool.tend = cv.take<double>(2 * cap);
+    c->pool.src = cv.take<uint32_t>(cap);
+    c->pool.pix = cv.take<uint32_t>(cap);
+    if (cv.used > kScratchBytes) return false;
+    c->pool.cap = cap;
+    return cap >= (12ull << (2 * c->p.level0));
+}
+
+// The status art_sync would report, written to the caller's device int.
+__global__ void k_status_out(const Counters* ct, unsigned long long expected, int* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t s = ct->c.status;
+    int rc = ART_OK;
+    if (s & kStOverflow) rc = ART_ERR_QUEUE_OVERFLOW;
+    else if (s & kStOutside) rc = ART_ERR_SOURCE_OUTSIDE;
+    else if (s & kStBadField) rc = ART_ERR_BAD_FIELD;
+    else if (s & kStStuck) rc = ART_ERR_INVALID_ARG;
+    else if (ct->c.destroy != expected) rc = ART_ERR_DESTROY_COUNT;
+    *out = rc;
+}
+
+}  // namespace
+
+extern "C" int art_trace_noalloc(int nx, int ny, int nz, const art_params* params, const float* n_H,
+                                 const float* x_n, const double* src_pos, const float* src_lum, int n_src,
+                                 float* rate, float* force, float* J, int* status, void* stream) {
+    if (nx <= 0 || ny <= 0 || nz <= 0 || !n_H || !x_n || !rate || !force || n_src < 0) return ART_ERR_INVALID_ARG;
+    if (n_src > 0 && (!src_pos || !src_lum)) return ART_ERR_INVALID_ARG;
+    int rc = check_params(params);
+    if (rc) return rc;
+    const uint64_t N = (uint64_t)nx * ny * nz;
+    if (N >= (1ull << 32)) return ART_ERR_INVALID_ARG;
+    art_ctx c{};
+    c.nx = nx;
+    c.ny = ny;
+    c.nz = nz;
+    c.N = N;
+    c.p = *params;
+    c.o.max_sources = std::max(1, n_src);
+    c.o.block_size = 64;
+    c.o.blocks_per_cu = 16;
+    c.stream = (hipStream_t)stream;
+    init_geometry(&c, nx, ny, nz, *params);
+    // sizes first, on a null base: no device is touched for an input that cannot fit
+    if (!noalloc_layout(&c, nullptr, n_src, J != nullptr)) return ART_ERR_TOO_LARGE;
+    if (hipGetDevice(&c.device) != hipSuccess ||
+        hipDeviceGetAttribute(&c.cu_count, hipDeviceAttributeMultiprocessorCount, c.device) != hipSuccess)
+        return ART_ERR_HIP;
+    unsigned char* base = nullptr;
+    if ((rc = scratch_on_device(c.device, &base))) return rc;
+    noalloc_layout(&c, base, n_src, J != nullptr);
+    c.wave_max = (int)std::max<uint64_t>(1, std::min<uint64_t>(c.pool.cap / std::max<uint64_t>(c.per_src_bound, 1),
+                                                                (uint64_t)c.o.max_sources));
+    Mat3 r;
+    for (int i = 0; i < 9; ++i) r.m[i] = params->rot[i];
+    hipLaunchKernelGGL(k_set_rot, dim3(1), dim3(64), 0, c.stream, r, c.rot);
+    HIP_TRY(hipGetLastError());
+    c.geo.rot = c.rot;
+    if ((rc = trace_impl(&c, n_H, x_n, src_pos, src_lum, n_src, rate, force, J))) return rc;
+    if (status) {
+        hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, c.stream, c.ct,
+                           (unsigned long long)destroy_expected(&c, n_src), status);
+        HIP_TRY(hipGetLastError());
+    }
+    return ART_OK;
+}

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 def test_error_strings():
     from paper_1711_06277_amd import _abi as A
     assert A.strerror(A.ART_OK) == "ok"
-    for code in range(-9, 0):
+    for code in range(-10, 0):
         assert A.strerror(code) != "unknown error"
     assert A.strerror(-99) == "unknown error"
 
@@ -76,3 +76,22 @@ def test_create_without_gpu_fails_cleanly():
         with pytest.raises(A.ArtError) as e:
             A.art_create(8, 8, 8, p, o, 0)
         assert e.value.code == A.ART_ERR_INVALID_ARG, bad
+
+
+def test_noalloc_rejects_inputs_beyond_its_workspace():
+    """art_trace_noalloc checks the sizes against its static workspace before it
+    touches a device: a grid whose fixed parts cannot fit is refused with
+    ART_ERR_TOO_LARGE (the pointers are never read)."""
+    import ctypes as C
+    from paper_1711_06277_amd import _abi as A
+    p = A.art_params()
+    p.level0, p.level_max, p.phi_c, p.tau_term, p.s_H, p.n_bins = 2, 13, 4.0, 23.0, 0.1, 1
+    p.rot[0] = p.rot[4] = p.rot[8] = 1.0
+    fake = C.c_void_p(256)
+    n = 1024  # 72 bytes per cell alone exceed the workspace
+    with pytest.raises(A.ArtError) as e:
+        A.art_trace_noalloc(n, n, n, p, fake, fake, fake, fake, 1, fake, fake, None, None, 0)
+    assert e.value.code == A.ART_ERR_TOO_LARGE
+    with pytest.raises(A.ArtError) as e:  # null fields
+        A.art_trace_noalloc(8, 8, 8, p, None, fake, fake, fake, 1, fake, fake, None, None, 0)
+    assert e.value.code == A.ART_ERR_INVALID_ARG
