@@ -97,13 +97,18 @@ def test_workload3_batched_full_size(wl3, refs3, deterministic):
     compare_cells("batched vs plain rate", rate_b.cpu().numpy(), acc_r.cpu().numpy(), L)
 
 
+@pytest.fixture(scope="module")
+def adj4(oracle):
+    wl = I.config(4)
+    return wl, oracle.adjoint(wl.nx, wl.ny, wl.nz, wl.n_H, wl.x_n, wl.src_pos, wl.src_lum, wl.w, wl.v,
+                              **wl.params())
+
+
 @pytest.mark.parametrize("deterministic", [False, True], ids=["fp64_accumulator", "fixed_point"])
-def test_workload4_adjoint_full_size(oracle, deterministic):
+def test_workload4_adjoint_full_size(adj4, deterministic):
     """128^3, sigmoid x_n, 8 sources: GPU adjoint (over the stored tree, as the
     benchmark runs it) vs the FP64 oracle adjoint, in both accumulator modes."""
-    wl = I.config(4)
-    ref_nH, ref_xn = oracle.adjoint(wl.nx, wl.ny, wl.nz, wl.n_H, wl.x_n, wl.src_pos, wl.src_lum,
-                                    wl.w, wl.v, **wl.params())
+    wl, (ref_nH, ref_xn) = adj4
     tr = tracer(wl, max_sources=wl.n_src, enable_adjoint=True, deterministic=deterministic)
     try:
         args = (dev(wl.n_H), dev(wl.x_n), dev(wl.src_pos), dev(wl.src_lum))
