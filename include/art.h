@@ -307,7 +307,7 @@ const char *art_strerror(int code);
  *                            art_sync would report
  *   stream                   hipStream_t the kernels are enqueued on (NULL = null stream)
  * Sources are traced in waves that fit what is left of the array after the
- * fixed parts (about 72 bytes per cell and 300 per source), at 40 bytes per ray.
+ * fixed parts (about 76 bytes per cell and 300 per source), at 40 bytes per ray.
  * ART_ERR_TOO_LARGE, with nothing enqueued, if the fixed parts or one source's
  * seed rays do not fit; a tree larger than the pool is reported as
  * ART_ERR_QUEUE_OVERFLOW in *status.  Every call on a GPU uses that GPU's one

@@ -122,6 +122,7 @@ __global__ void k_zero_stats(SrcStats st, uint64_t ms) {
 struct SweepArgs {
     Geo g;
     const float2* q;   // (n_H, x_n) per cell, packed once per call
+    const float* fg;   // gas share of the ionizing opacity per cell
     const float* nH;
     const float* xn;
     const double* src_pos;
@@ -193,14 +194,20 @@ __global__ void k_fill_f64(double* p, uint64_t n) {
 // ignores (no gas as far as the sweep is concerned).
 // The fields are also checked here (the pass reads every cell anyway): a cell with
 // n_H < 0 or not finite, or x_n outside [0, 1], sets kStBadField.
+// fg[c] = x_n s_H / (x_n s_H + s_d): the gas's share of the ionizing bin's opacity,
+// which turns a segment's absorbed ionizing luminosity into its photoionizations
+// (Eq. e:photrate2); 0 where nothing absorbs.
 __global__ void k_pack(uint64_t N, const float* nH, const float* xn, const uint8_t* transparent, float2* q,
-                       Counters* ct) {
+                       float* fg, double s_H, double s_d, Counters* ct) {
     bool bad = false;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const float n = nH[i], x = xn[i];
         bad = bad || !(n >= 0.0f && n <= 3.4e38f) || !(x >= 0.0f && x <= 1.0f);
-        q[i] = make_float2((transparent && transparent[i]) ? 0.0f : n, x);
+        const bool sink = transparent && transparent[i];
+        q[i] = make_float2(sink ? 0.0f : n, x);
+        const double gas = (double)x * s_H, chi = gas + s_d;
+        fg[i] = (sink || !(chi > 0.0)) ? 0.0f : (float)(gas / chi);
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ct->c.status, (uint32_t)kStBadField);
 }
@@ -845,11 +852,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
             for (int b = 0; b < NB; ++b) lnom[b] = a.src_lum[(uint64_t)src * NB + b] * lnom_scale;
             if (bad_src || !source_inside(g, r.xs)) bad_src = true;
-            else if (!r.starts_outside) march_begin(g, a.q, r, m);
+            else if (!r.starts_outside) march_begin(g, a.q, r, m, MODE ? a.fg : nullptr);
         }
         // converged march: one segment per lane per iteration
         const float nxf = (float)r.n[0], nyf = (float)r.n[1], nzf = (float)r.n[2];
-        const float sHf = (float)g.s_H, sdf = (float)g.s_d;
         // The loop body twice per iteration: the march state then alternates
         // between two register sets instead of being copied back every step.
         auto step = [&]() __attribute__((always_inline)) {
@@ -873,7 +879,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                 uint32_t c;
                 int ijk[3];
                 double dr, dtau[NB], tin[NB];
-                const bool seg = march_step<NB>(g, a.q, r, m, tau, &stuck, c, ijk, dr, dtau, tin);
+                const float fgc = m.fg;  // this step's cell, before march_step moves on
+                const bool seg =
+                    march_step<NB>(g, a.q, r, m, tau, &stuck, c, ijk, dr, dtau, tin, MODE ? a.fg : nullptr);
                 if (seg) ++nseg;
                 if (MODE) {
                     // without a segment the key below is empty: the quad combine
@@ -900,12 +908,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                             }
                         }
                         // the gas's share of the ionizing bin's absorption (Sec. 2.3
-                        // opacities): n_H x_n s_H / (n_H (x_n s_H + s_d)); zero where the
-                        // cell is empty or transparent (no absorption there)
-                        const float gas = qv.y * sHf;
-                        const float chi = gas + sdf;
-                        const float fgas = chi > 0.0f ? gas * __builtin_amdgcn_rcpf(chi) : 0.0f;
-                        v[SV::kRate] = fgas * dL0;
+                        // opacities), gathered with the cell's fields
+                        v[SV::kRate] = fgc * dL0;
                         v[1] = nxf * dLs;
                         v[2] = nyf * dLs;
                         v[3] = nzf * dLs;
@@ -1504,6 +1508,7 @@ struct art_ctx {
     double* rot;              // [9] rotation of the ray directions read by the sweeps
     const uint8_t* transparent = nullptr;  // caller's per-cell sink flags, or none
     float2* q;                // [N] packed (n_H, x_n)
+    float* fg;                // [N] gas share of the ionizing opacity
     float4* wv;               // [N] packed adjoint weights (w, v_x, v_y, v_z)
     int n_shell;                // levels whose radial shells one cell can meet (fixed-point bound)
     // tape of the last forward: its tree stays in the pool (single-wave traces only)
@@ -1681,6 +1686,7 @@ void free_all(art_ctx* c) {
     (void)hipFree(c->ion);
     (void)hipFree(c->rot);
     (void)hipFree(c->q);
+    (void)hipFree(c->fg);
     (void)hipFree(c->wv);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->ev_call0) (void)hipEventDestroy(c->ev_call0);
@@ -1699,6 +1705,7 @@ SweepArgs sweep_args(art_ctx* c, const float* nH, const float* xn, const double*
     SweepArgs a;
     a.g = c->geo;
     a.q = c->q;
+    a.fg = c->fg;
     a.nH = nH;
     a.xn = xn;
     a.src_pos = pos;
@@ -1820,7 +1827,7 @@ int begin_call(art_ctx* c, const float* lum, int n_src, const float* nH, const f
                        c->n_shell);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_pack, dim3(fill_blocks(c->N)), dim3(256), 0, c->stream, c->N, nH, xn, c->transparent,
-                       c->q, c->ct);
+                       c->q, c->fg, c->p.s_H, c->p.s_d, c->ct);
     HIP_TRY(hipGetLastError());
     return ART_OK;
 }
@@ -1918,7 +1925,7 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
              dmalloc(&c->pool.rlast, cap) && dmalloc(&c->pool.taulast, 2 * cap);
     // one spare cell: the sweep's deposit cache flushes cells in pairs (2g, 2g + 1)
     if (ok) ok = det ? dmalloc(&c->det, 8 * (N + 1)) : dmalloc(&c->acc, 8 * (N + 1));
-    if (ok) ok = dmalloc(&c->q, N);
+    if (ok) ok = dmalloc(&c->q, N) && dmalloc(&c->fg, N);
     if (ok && o.enable_adjoint) ok = det ? dmalloc(&c->gdet, 2 * N) : dmalloc(&c->gk, 2 * N);
     if (ok && o.enable_adjoint) ok = dmalloc(&c->wv, N);
     if (ok) {
@@ -2492,6 +2499,7 @@ bool noalloc_layout(art_ctx* c, unsigned char* base, int n_src, bool want_J) {
     c->st.segments = cv.take<unsigned long long>(ms);
     c->rot = cv.take<double>(9);
     c->q = cv.take<float2>(N);
+    c->fg = cv.take<float>(N);
     const uint64_t n_acc = (uint64_t)(want_J ? 8 : 4) * (N + (N & 1));
     if (c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC) c->det = cv.take<unsigned long long>(n_acc);
     else c->acc = cv.take<float>(n_acc);

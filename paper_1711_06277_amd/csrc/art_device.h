@@ -169,6 +169,7 @@ struct MarchState {
     double rr;
     uint32_t c;       // linear index of the current cell
     float2 q;         // (n_H, x_n) of the current cell
+    float fg;         // the gas's share of the ionizing opacity in the current cell (if gathered)
     int it, max_steps;
     bool alive;
     int end;
@@ -199,7 +200,8 @@ __device__ __forceinline__ uint32_t cell_index(const Geo& g, const int (&cell)[3
     return ((uint32_t)cell[2] * (uint32_t)g.ny + (uint32_t)cell[1]) * (uint32_t)g.nx + (uint32_t)cell[0];
 }
 
-__device__ inline void march_begin(const Geo& g, const float2* __restrict__ q, const Ray& r, MarchState& m) {
+__device__ inline void march_begin(const Geo& g, const float2* __restrict__ q, const Ray& r, MarchState& m,
+                                   const float* __restrict__ fg = nullptr) {
     const int dims[3] = {g.nx, g.ny, g.nz};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -214,6 +216,7 @@ __device__ inline void march_begin(const Geo& g, const float2* __restrict__ q, c
     m.rr = r.r_a;
     m.c = cell_index(g, m.cell);
     m.q = q[m.c];
+    if (fg) m.fg = fg[m.c];
     m.it = 0;
     m.max_steps = g.nx + g.ny + g.nz + 8;
     m.alive = true;
@@ -228,7 +231,8 @@ __device__ inline void march_begin(const Geo& g, const float2* __restrict__ q, c
 template <int NB>
 __device__ __forceinline__ bool march_step(const Geo& g, const float2* __restrict__ q, const Ray& r,
                                            MarchState& m, double (&tau)[NB], bool* stuck, uint32_t& c,
-                                           int (&ijk)[3], double& dr, double (&dtau)[NB], double (&tin)[NB]) {
+                                           int (&ijk)[3], double& dr, double (&dtau)[NB], double (&tin)[NB],
+                                           const float* __restrict__ fg = nullptr) {
     const int dims[3] = {g.nx, g.ny, g.nz};
     const bool alive = m.alive;
     const bool budget = m.it < m.max_steps;
@@ -289,7 +293,10 @@ __device__ __forceinline__ bool march_step(const Geo& g, const float2* __restric
 #pragma unroll
     for (int a = 0; a < 3; ++a) c2 += (adv & st[a]) ? r.dc[a] : 0u;
     m.c = c2;
-    if (adv) m.q = q[c2];  // prefetch for the next step
+    if (adv) {  // prefetch for the next step
+        m.q = q[c2];
+        if (fg) m.fg = fg[c2];
+    }
     return seg;
 }
 

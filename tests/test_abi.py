@@ -88,7 +88,7 @@ def test_noalloc_rejects_inputs_beyond_its_workspace():
     p.level0, p.level_max, p.phi_c, p.tau_term, p.s_H, p.n_bins = 2, 13, 4.0, 23.0, 0.1, 1
     p.rot[0] = p.rot[4] = p.rot[8] = 1.0
     fake = C.c_void_p(256)
-    n = 1024  # 72 bytes per cell alone exceed the workspace
+    n = 1024  # 76 bytes per cell alone exceed the workspace
     with pytest.raises(A.ArtError) as e:
         A.art_trace_noalloc(n, n, n, p, fake, fake, fake, fake, 1, fake, fake, None, None, 0)
     assert e.value.code == A.ART_ERR_TOO_LARGE
