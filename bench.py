@@ -261,10 +261,6 @@ def main():
     if rc != 0:
         log(f"[bench] device status {rc} after warm-up")
         sys.exit(1)
-    st = tr.stats(wl.n_src)
-    segments = st.segments
-    log(f"[bench] {segments} segments per trace, {st.n_waves} wave(s), "
-        f"rays in the largest wave {st.rays_max_wave}")
 
     torch.cuda.synchronize()
     tr.set_timing(True)
@@ -283,6 +279,10 @@ def main():
     if rc != 0:
         log(f"[bench] device status {rc}")
         sys.exit(1)
+    st = tr.stats(wl.n_src)  # of the last timed trace (every trace makes the same segments)
+    segments = st.segments
+    log(f"[bench] {segments} segments per trace, {st.n_waves} wave(s), "
+        f"rays in the largest wave {st.rays_max_wave}")
     ms_per_step = 1e3 * t_total / args.steps
     seg_per_s = segments * args.steps / t_total
     ms_per_source = ms_per_step / wl.n_src
