@@ -202,8 +202,9 @@ def main():
                     help="FP32 atomic deposits instead of the (faster) 64-bit fixed-point ones")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="pick the sweep's launch shape with art_autotune before timing")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (launch shapes, sources per wave); by default its "
+                         "cached result for this GPU and workload is applied, or it runs once and is cached")
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     args = ap.parse_args()
@@ -235,10 +236,15 @@ def main():
     dev = torch.device("cuda:0")
 
     def make_tracer(**kw):
+        shape = (args.block_size, args.blocks_per_cu)
+        if tuned is not None:
+            shape = (tuned["block_size"], tuned["blocks_per_cu"])
         return ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
                          level0=wl.level0, level_max=wl.level_max, phi_c=wl.phi_c,
                          tau_term=wl.tau_term, deterministic=wl.deterministic,
-                         block_size=args.block_size, blocks_per_cu=args.blocks_per_cu, device=dev, **kw)
+                         block_size=shape[0], blocks_per_cu=shape[1], device=dev, **kw)
+
+    tuned = None
 
     tr = make_tracer(max_sources=wl.n_src)
     nH = torch.from_numpy(wl.n_H).to(dev)
@@ -250,9 +256,13 @@ def main():
     force = torch.empty((3, N), dtype=torch.float32, device=dev)
     out = (rate, force, None)
 
-    if args.autotune:
-        bb, bp, ms = tr.autotune(nH, xn, pos, lum)
-        log(f"[bench] autotune: {bb} threads x {bp} workgroups per CU ({ms:.1f} ms)")
+    if not args.no_autotune and not (args.block_size or args.blocks_per_cu):
+        ta0 = time.perf_counter()
+        bb, bp, bw, ms = tr.autotune(nH, xn, pos, lum, cache=True)
+        tuned = {"block_size": bb, "blocks_per_cu": bp, "wave_sources": bw, "ms": ms,
+                 "s_spent": time.perf_counter() - ta0}
+        log(f"[bench] autotune: {bb} threads x {bp} workgroups per CU, wave cap {bw or 'none'} "
+            f"({ms:.1f} ms, {tuned['s_spent']:.1f} s)")
 
     # ---- batched: all sources in one call ----
     for _ in range(args.warmup):
@@ -350,6 +360,12 @@ def main():
         w_np, v_np = I.random_adjoint_weights(N, seed=7000 + args.workload)
         w = torch.from_numpy(w_np).to(dev)
         v = torch.from_numpy(v_np).to(dev)
+        if tuned is not None:
+            if tuned["wave_sources"]:
+                ta.set_wave_sources(tuned["wave_sources"])
+            ab, ap, ams = ta.autotune_adjoint(nH, xn, pos, lum, w, v, cache=True)
+            tuned["adjoint"] = {"block_size": ab, "blocks_per_cu": ap, "ms": ams}
+            log(f"[bench] adjoint autotune: {ab} threads x {ap} workgroups per CU ({ams:.1f} ms)")
         g_nH = torch.empty(N, dtype=torch.float32, device=dev)
         g_xn = torch.empty(N, dtype=torch.float32, device=dev)
         ta.trace(nH, xn, pos, lum, out=out, check=False)
@@ -573,6 +589,7 @@ def main():
         "adjoint": adjoint,
         "ion_subcycle": ion,
         "workload5_forward_adjoint_graph": w5,
+        "autotune": tuned,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

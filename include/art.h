@@ -189,19 +189,38 @@ int art_get_stats(art_ctx *ctx, art_stats *out, int stats_sources, uint32_t *src
                   uint32_t *src_split, uint32_t *src_exited, uint32_t *src_terminated,
                   double *src_escaped, double *src_residual, uint64_t *src_segments);
 
-/* Time the forward sweep on the given inputs for each candidate launch shape
- * (block_size x blocks_per_cu from the built-in list) and keep the fastest in
- * the context; writes the chosen pair and its time in milliseconds.  Runs the
- * sweep several times and synchronises; outputs hold the last run. */
+/* Autotuning (times real runs on the given inputs, synchronises; outputs hold the
+ * last run).  art_autotune times the forward sweep for each launch shape of a
+ * built-in list (threads per workgroup x workgroups per CU), then, with the
+ * fastest shape, caps of n_src/2 and n_src/4 sources per wave against as many as
+ * the pool holds (a cap is kept only if at least 1% faster); it keeps the winners
+ * in the context and writes them (best_wave_sources 0 = no cap) with the best time
+ * in milliseconds.  Any output pointer may be NULL. */
 int art_autotune(art_ctx *ctx, const float *n_H, const float *x_n, const double *src_pos,
                  const float *src_lum, int n_src, float *rate, float *force,
-                 int *best_block_size, int *best_blocks_per_cu, float *best_ms);
+                 int *best_block_size, int *best_blocks_per_cu, int *best_wave_sources, float *best_ms);
+
+/* The same for the adjoint sweep's launch shape (separate from the forward's): one
+ * art_trace, then adjoints over its stored tree (or full adjoints if the sources
+ * need several waves) for each shape.  Requires enable_adjoint. */
+int art_autotune_adjoint(art_ctx *ctx, const float *n_H, const float *x_n, const double *src_pos,
+                         const float *src_lum, int n_src, float *rate, float *force,
+                         const float *g_rate, const float *g_force, float *g_nH, float *g_xn,
+                         int *best_block_size, int *best_blocks_per_cu, float *best_ms);
 
 /* Set the launch shape of the sweep kernels (as art_options.block_size and
  * blocks_per_cu; 0 selects the default), e.g. a shape art_autotune found earlier
  * for the same grid and source count.  ART_ERR_INVALID_ARG for a shape outside the
  * ranges art_create accepts. */
 int art_set_launch(art_ctx *ctx, int block_size, int blocks_per_cu);
+
+/* The same for the adjoint sweep kernels (art_create starts them at the forward's). */
+int art_set_adjoint_launch(art_ctx *ctx, int block_size, int blocks_per_cu);
+
+/* Trace at most this many sources per wave (0: as many as the pool holds).  Results
+ * do not depend on it (bitwise, in the deterministic mode); with more than one wave
+ * no tape is kept.  Clears the stored tape. */
+int art_set_wave_sources(art_ctx *ctx, int max_sources_per_wave);
 
 /* Average duration in ms of the per-level sweep launches of the last forward
  * call (HIP events on the context's stream; enable with art_set_timing). */

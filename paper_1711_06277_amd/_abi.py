@@ -32,7 +32,8 @@ ART_MAX_BINS = 2
 # every symbol declared in include/art.h
 EXPORTED = ("art_create", "art_set_stream", "art_trace", "art_get_tape", "art_trace_adjoint",
             "art_trace_adjoint_tape", "art_trace_and_adjoint", "art_sync",
-            "art_get_stats", "art_autotune", "art_set_launch", "art_set_timing", "art_get_timing",
+            "art_get_stats", "art_autotune", "art_autotune_adjoint", "art_set_launch",
+            "art_set_adjoint_launch", "art_set_wave_sources", "art_set_timing", "art_get_timing",
             "art_set_transparent", "art_set_rotation", "art_random_rotation", "art_get_rotation",
             "art_ion_substep", "art_ion_subcycle", "art_destroy", "art_strerror", "art_trace_noalloc")
 
@@ -91,8 +92,12 @@ def lib() -> C.CDLL:
         L.art_sync.argtypes = [vp]
         L.art_get_stats.argtypes = [vp, C.POINTER(art_stats), C.c_int, vp, vp, vp, vp, vp, vp, vp]
         L.art_autotune.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, C.POINTER(C.c_int),
-                                   C.POINTER(C.c_int), C.POINTER(C.c_float)]
+                                   C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_float)]
+        L.art_autotune_adjoint.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp, vp, vp, vp,
+                                           C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_float)]
         L.art_set_launch.argtypes = [vp, C.c_int, C.c_int]
+        L.art_set_adjoint_launch.argtypes = [vp, C.c_int, C.c_int]
+        L.art_set_wave_sources.argtypes = [vp, C.c_int]
         L.art_set_timing.argtypes = [vp, C.c_int]
         L.art_get_timing.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_int),
                                      C.POINTER(C.c_float)]
@@ -181,14 +186,31 @@ def art_get_stats(ctx, n_src_stats, created, split, exited, terminated, escaped,
 
 
 def art_autotune(ctx, n_H, x_n, src_pos, src_lum, n_src, rate, force):
-    bb, bp, ms = C.c_int(), C.c_int(), C.c_float()
+    bb, bp, bw, ms = C.c_int(), C.c_int(), C.c_int(), C.c_float()
     check(lib().art_autotune(C.c_void_p(ctx), n_H, x_n, src_pos, src_lum, int(n_src), rate, force,
-                             C.byref(bb), C.byref(bp), C.byref(ms)), "art_autotune")
+                             C.byref(bb), C.byref(bp), C.byref(bw), C.byref(ms)), "art_autotune")
+    return bb.value, bp.value, bw.value, ms.value
+
+
+def art_autotune_adjoint(ctx, n_H, x_n, src_pos, src_lum, n_src, rate, force, g_rate, g_force, g_nH, g_xn):
+    bb, bp, ms = C.c_int(), C.c_int(), C.c_float()
+    check(lib().art_autotune_adjoint(C.c_void_p(ctx), n_H, x_n, src_pos, src_lum, int(n_src), rate, force,
+                                     g_rate, g_force, g_nH, g_xn, C.byref(bb), C.byref(bp), C.byref(ms)),
+          "art_autotune_adjoint")
     return bb.value, bp.value, ms.value
 
 
 def art_set_launch(ctx, block_size: int, blocks_per_cu: int):
     check(lib().art_set_launch(C.c_void_p(ctx), int(block_size), int(blocks_per_cu)), "art_set_launch")
+
+
+def art_set_adjoint_launch(ctx, block_size: int, blocks_per_cu: int):
+    check(lib().art_set_adjoint_launch(C.c_void_p(ctx), int(block_size), int(blocks_per_cu)),
+          "art_set_adjoint_launch")
+
+
+def art_set_wave_sources(ctx, n: int):
+    check(lib().art_set_wave_sources(C.c_void_p(ctx), int(n)), "art_set_wave_sources")
 
 
 def art_set_timing(ctx, enable: bool):

@@ -310,43 +310,80 @@ class ArtTracer:
             src_escaped=esc[:n, : self.n_bins], src_residual=res[:n, : self.n_bins],
             src_segments=seg[:n].astype(np.int64))
 
-    def autotune_key(self, n_src: int) -> str:
-        """Cache key of a launch shape: GPU name, grid, sources, bins, deposit mode, levels, m_ray."""
+    def autotune_key(self, n_src: int, kind: str = "sweep") -> str:
+        """Cache key of a tuned setting: what is tuned ("sweep": launch shape and sources
+        per wave; "adjoint": the adjoint's launch shape), GPU name, grid, sources, bins,
+        deposit mode, levels, m_ray, pool capacity."""
         p = self.params
-        return "|".join([torch.cuda.get_device_name(self.device), "x".join(map(str, self.shape)),
+        return "|".join([kind, torch.cuda.get_device_name(self.device), "x".join(map(str, self.shape)),
                          f"src{int(n_src)}", f"bins{self.n_bins}", f"mode{p.deposit_mode}",
-                         f"l{p.level0}-{p.level_max}", f"m{p.phi_c:g}"])
+                         f"l{p.level0}-{p.level_max}", f"m{p.phi_c:g}", f"adj{self.options.enable_adjoint}",
+                         f"pool{self.options.pool_rays}"])
 
-    def autotune(self, n_H, x_n, src_pos, src_lum, *, cache=None):
-        """Time the built-in launch shapes on these inputs and keep the fastest; returns
-        (block_size, blocks_per_cu, ms).  With ``cache`` (a JSON file path, or True for
-        $ART_AUTOTUNE_CACHE or ~/.cache/art_mi355x/autotune.json) a shape found before
-        for the same key is applied without timing, and new results are stored."""
-        path = autotune_cache_path(cache)
-        n_src = int(np.asarray(src_pos).reshape(-1, 3).shape[0]) if not isinstance(src_pos, torch.Tensor) \
-            else int(src_pos.reshape(-1, 3).shape[0])
-        if path is not None:
-            hit = load_autotune_cache(path).get(self.autotune_key(n_src))
-            if hit is not None:
-                A.art_set_launch(self._ctx, hit[0], hit[1])
-                return int(hit[0]), int(hit[1]), float(hit[2])
-        result = self._autotune(n_H, x_n, src_pos, src_lum)
-        if path is not None:
-            store_autotune_cache(path, self.autotune_key(n_src), result)
-        return result
-
-    def _autotune(self, n_H, x_n, src_pos, src_lum):
+    def _inputs(self, n_H, x_n, src_pos, src_lum):
         d = self.device
         n_H = _dev(n_H, torch.float32, d).reshape(-1)
         x_n = _dev(x_n, torch.float32, d).reshape(-1)
         src_pos = _dev(src_pos, torch.float64, d).reshape(-1, 3)
-        n_src = src_pos.shape[0]
-        src_lum = _dev(src_lum, torch.float32, d).reshape(n_src, self.n_bins)
+        src_lum = _dev(src_lum, torch.float32, d).reshape(src_pos.shape[0], self.n_bins)
+        return n_H, x_n, src_pos, src_lum
+
+    def autotune(self, n_H, x_n, src_pos, src_lum, *, cache=None):
+        """Time the built-in launch shapes, then caps on the sources per wave, on these
+        inputs and keep the fastest; returns (block_size, blocks_per_cu, wave_sources, ms),
+        wave_sources 0 meaning no cap.  With ``cache`` (a JSON file path, or True for
+        $ART_AUTOTUNE_CACHE or ~/.cache/art_mi355x/autotune.json) a setting found before
+        for the same key is applied without timing, and new results are stored."""
+        n_H, x_n, src_pos, src_lum = self._inputs(n_H, x_n, src_pos, src_lum)
+        n_src = int(src_pos.shape[0])
+        path = autotune_cache_path(cache)
+        key = self.autotune_key(n_src, "sweep")
+        if path is not None:
+            hit = load_autotune_cache(path).get(key)
+            if hit is not None and len(hit) == 4:
+                A.art_set_launch(self._ctx, hit[0], hit[1])
+                A.art_set_wave_sources(self._ctx, hit[2])
+                return int(hit[0]), int(hit[1]), int(hit[2]), float(hit[3])
+        rate = torch.empty(self.N, dtype=torch.float32, device=self.device)
+        force = torch.empty((3, self.N), dtype=torch.float32, device=self.device)
+        self._stream()
+        result = A.art_autotune(self._ctx, _ptr(n_H), _ptr(x_n), _ptr(src_pos), _ptr(src_lum), n_src,
+                                _ptr(rate), _ptr(force))
+        if path is not None:
+            store_autotune_cache(path, key, result)
+        return result
+
+    def autotune_adjoint(self, n_H, x_n, src_pos, src_lum, g_rate, g_force, *, cache=None):
+        """The adjoint sweep's launch shape, likewise; returns (block_size, blocks_per_cu, ms)."""
+        n_H, x_n, src_pos, src_lum = self._inputs(n_H, x_n, src_pos, src_lum)
+        n_src = int(src_pos.shape[0])
+        path = autotune_cache_path(cache)
+        key = self.autotune_key(n_src, "adjoint")
+        if path is not None:
+            hit = load_autotune_cache(path).get(key)
+            if hit is not None and len(hit) == 3:
+                A.art_set_adjoint_launch(self._ctx, hit[0], hit[1])
+                return int(hit[0]), int(hit[1]), float(hit[2])
+        d = self.device
+        g_rate = _dev(g_rate, torch.float32, d).reshape(-1)
+        g_force = _dev(g_force, torch.float32, d).reshape(3, -1)
         rate = torch.empty(self.N, dtype=torch.float32, device=d)
         force = torch.empty((3, self.N), dtype=torch.float32, device=d)
+        g_nH = torch.empty(self.N, dtype=torch.float32, device=d)
+        g_xn = torch.empty(self.N, dtype=torch.float32, device=d)
         self._stream()
-        return A.art_autotune(self._ctx, _ptr(n_H), _ptr(x_n), _ptr(src_pos), _ptr(src_lum), n_src,
-                              _ptr(rate), _ptr(force))
+        result = A.art_autotune_adjoint(self._ctx, _ptr(n_H), _ptr(x_n), _ptr(src_pos), _ptr(src_lum), n_src,
+                                        _ptr(rate), _ptr(force), _ptr(g_rate), _ptr(g_force), _ptr(g_nH),
+                                        _ptr(g_xn))
+        self.last_tape = 0
+        self._tape_inputs = None
+        if path is not None:
+            store_autotune_cache(path, key, result)
+        return result
+
+    def set_wave_sources(self, n: int):
+        """Trace at most n sources per wave (0: as many as the pool holds)."""
+        A.art_set_wave_sources(self._ctx, int(n))
 
     def set_timing(self, enable: bool):
         A.art_set_timing(self._ctx, enable)
@@ -376,9 +413,9 @@ def load_autotune_cache(path) -> dict:
 
 
 def store_autotune_cache(path, key, result) -> None:
-    """Add one (block_size, blocks_per_cu, ms) entry, replacing the file atomically."""
+    """Add one entry (integers, then the time in ms last), replacing the file atomically."""
     data = load_autotune_cache(path)
-    data[key] = [int(result[0]), int(result[1]), float(result[2])]
+    data[key] = [int(x) for x in result[:-1]] + [float(result[-1])]
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     tmp = f"{path}.{os.getpid()}.tmp"
     with open(tmp, "w") as f:

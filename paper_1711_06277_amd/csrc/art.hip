@@ -1494,7 +1494,10 @@ struct art_ctx {
     Geo geo;
     Pool pool;
     uint64_t per_src_bound;
-    int wave_max;
+    int wave_max;               // sources the pool holds in one wave
+    int wave_cap = 0;           // at most this many sources per wave (0: wave_max)
+    int adj_block = 64;         // launch shape of the adjoint sweeps
+    int adj_bpc = 16;
     int cur_wave = 1;           // sources in the wave being swept (sizes the shallow levels' grids)
     int deepest;                // deepest level that can hold rays in this grid
     Counters* ct;
@@ -1737,14 +1740,17 @@ uint64_t level_rays_bound(const art_ctx* c, int level) {
     return std::min<uint64_t>(all, c->pool.cap);
 }
 
-unsigned level_blocks(const art_ctx* c, int level) {
-    const uint64_t full = (uint64_t)c->cu_count * (uint64_t)c->o.blocks_per_cu;
-    const uint64_t need = (level_rays_bound(c, level) + c->o.block_size - 1) / c->o.block_size;
+unsigned level_blocks(const art_ctx* c, int level, int block, int per_cu) {
+    const uint64_t full = (uint64_t)c->cu_count * (uint64_t)per_cu;
+    const uint64_t need = (level_rays_bound(c, level) + block - 1) / block;
     return (unsigned)std::max<uint64_t>(1, std::min(full, need));
 }
 
+// Sources per wave: what the pool holds, or the tuned cap if smaller.
+int wave_len(const art_ctx* c) { return c->wave_cap > 0 ? std::min(c->wave_cap, c->wave_max) : c->wave_max; }
+
 int launch_sweep(art_ctx* c, const SweepArgs& a, int level, int mode) {
-    const dim3 grid(level_blocks(c, level)), block((unsigned)c->o.block_size);
+    const dim3 grid(level_blocks(c, level, c->o.block_size, c->o.blocks_per_cu)), block((unsigned)c->o.block_size);
     const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
     const int nb = c->p.n_bins;
     const bool tm = c->timing && c->ev_used + 2 <= (int)c->ev.size();
@@ -1777,7 +1783,7 @@ int launch_sweep(art_ctx* c, const SweepArgs& a, int level, int mode) {
 }
 
 int launch_adjoint(art_ctx* c, const AdjArgs& a, int level) {
-    const dim3 grid(level_blocks(c, level)), block((unsigned)c->o.block_size);
+    const dim3 grid(level_blocks(c, level, c->adj_block, c->adj_bpc)), block((unsigned)c->adj_block);
     const bool det = c->p.deposit_mode == ART_DEPOSIT_DETERMINISTIC;
     const size_t lds = det ? adjoint_lds_bytes<1, true>(block.x) : adjoint_lds_bytes<1, false>(block.x);
     if (c->p.n_bins == 1) {
@@ -1881,6 +1887,8 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
     c->N = N;
     c->p = *params;
     c->o = o;
+    c->adj_block = o.block_size;
+    c->adj_bpc = o.blocks_per_cu;
     c->stream = (hipStream_t)stream;
     if (hipGetDevice(&c->device) != hipSuccess ||
         hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
@@ -1981,8 +1989,8 @@ int trace_impl(art_ctx* c, const float* n_H, const float* x_n, const double* src
     if ((rc = zero_stats(c, ms))) return rc;
     const SweepArgs a = sweep_args(c, n_H, x_n, src_pos, src_lum, force, J, n_src);
     int waves = 0;
-    for (int s0 = 0; s0 < n_src; s0 += c->wave_max) {
-        const int nw = std::min(c->wave_max, n_src - s0);
+    for (int s0 = 0; s0 < n_src; s0 += wave_len(c)) {
+        const int nw = std::min(wave_len(c), n_src - s0);
         if ((rc = seed_wave(c, s0, nw))) return rc;
         if ((rc = sweep_wave(c, a, mode))) return rc;
         ++waves;
@@ -2119,14 +2127,14 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
     if ((rc = begin_call(c, src_lum, n_src, n_H, x_n))) return rc;
     if ((rc = zero_stats(c, (uint64_t)c->o.max_sources))) return rc;
     const SweepArgs a = sweep_args(c, n_H, x_n, src_pos, src_lum, nullptr, nullptr, n_src);
-    for (int s0 = 0; s0 < n_src; s0 += c->wave_max) {
-        const int nw = std::min(c->wave_max, n_src - s0);
+    for (int s0 = 0; s0 < n_src; s0 += wave_len(c)) {
+        const int nw = std::min(wave_len(c), n_src - s0);
         if ((rc = seed_wave(c, s0, nw))) return rc;
         if ((rc = sweep_wave(c, a, 0))) return rc;
         if ((rc = adjoint_levels(c, aa))) return rc;
     }
     c->last_nsrc = n_src;
-    c->last_waves = (n_src + c->wave_max - 1) / c->wave_max;
+    c->last_waves = (n_src + wave_len(c) - 1) / wave_len(c);
     return adjoint_epilogue(c, g_nH, g_xn);
 }
 
@@ -2172,8 +2180,8 @@ int art_trace_and_adjoint(art_ctx* c, const float* n_H, const float* x_n, const 
     // each wave's tree is walked back right after its forward sweep, while the
     // pool still holds it: no wave is traced twice
     int waves = 0;
-    for (int s0 = 0; s0 < n_src; s0 += c->wave_max) {
-        const int nw = std::min(c->wave_max, n_src - s0);
+    for (int s0 = 0; s0 < n_src; s0 += wave_len(c)) {
+        const int nw = std::min(wave_len(c), n_src - s0);
         if ((rc = seed_wave(c, s0, nw))) return rc;
         if ((rc = sweep_wave(c, a, mode))) return rc;
         if ((rc = adjoint_levels(c, aa))) return rc;
@@ -2287,43 +2295,132 @@ int art_get_timing(art_ctx* c, float* sweep_ms_total, int* sweep_launches, float
     return ART_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Launch shapes the autotuner tries: (threads per workgroup, workgroups per CU).
+constexpr int kShapes[][2] = {{64, 8}, {64, 12}, {64, 16}, {128, 4}, {128, 6}, {256, 2}, {256, 4}};
+
+// The best of `reps` timed runs after one untimed run (HIP events on the stream).
+template <class F>
+int best_time(art_ctx* c, int reps, F&& run, float* best) {
+    *best = 1e30f;
+    for (int rep = 0; rep <= reps; ++rep) {
+        HIP_TRY(hipEventRecord(c->ev_call0, c->stream));
+        int rc = run();
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(c->ev_call1, c->stream));
+        HIP_TRY(hipEventSynchronize(c->ev_call1));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev_call0, c->ev_call1));
+        if (rep > 0) *best = std::min(*best, ms);
+    }
+    return ART_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int art_autotune(art_ctx* c, const float* n_H, const float* x_n, const double* src_pos, const float* src_lum,
-                 int n_src, float* rate, float* force, int* best_block, int* best_bpc, float* best_ms) {
-    if (!c) return ART_ERR_INVALID_ARG;
-    static const int cand[][2] = {{64, 8}, {64, 12}, {64, 16}, {128, 4}, {128, 6}, {256, 2}, {256, 4}};
+                 int n_src, float* rate, float* force, int* best_block, int* best_bpc, int* best_wave_sources,
+                 float* best_ms) {
+    if (!c || n_src < 1) return ART_ERR_INVALID_ARG;
     const art_options keep = c->o;
+    const int keep_cap = c->wave_cap;
     const bool keep_timing = c->timing;
-    c->timing = true;
+    c->timing = false;
+    auto run = [&]() { return art_trace(c, n_H, x_n, src_pos, src_lum, n_src, rate, force, nullptr); };
+    auto restore = [&](int rc) {
+        c->o = keep;
+        c->wave_cap = keep_cap;
+        c->timing = keep_timing;
+        return rc;
+    };
+    // 1. launch shapes, with as many sources per wave as the pool holds
     float best = 1e30f;
     int bb = keep.block_size, bp = keep.blocks_per_cu;
-    for (const auto& cd : cand) {
+    c->wave_cap = 0;
+    for (const auto& cd : kShapes) {
         c->o.block_size = cd[0];
         c->o.blocks_per_cu = cd[1];
-        float ms_best = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
-            int rc = art_trace(c, n_H, x_n, src_pos, src_lum, n_src, rate, force, nullptr);
-            if (rc) {
-                c->o = keep;
-                c->timing = keep_timing;
-                return rc;
-            }
-            float tot = 0.0f;
-            rc = art_get_timing(c, nullptr, nullptr, &tot);
-            if (rc) {
-                c->o = keep;
-                c->timing = keep_timing;
-                return rc;
-            }
-            if (rep > 0) ms_best = std::min(ms_best, tot);
-        }
-        if (ms_best < best) {
-            best = ms_best;
+        float ms;
+        int rc = best_time(c, 2, run, &ms);
+        if (rc) return restore(rc);
+        if (ms < best) {
+            best = ms;
             bb = cd[0];
             bp = cd[1];
         }
     }
     c->o.block_size = bb;
     c->o.blocks_per_cu = bp;
+    // 2. sources per wave (fewer sources per wave: a smaller working set per level,
+    //    but each wave repays the shallow levels and the launches)
+    int bw = 0;
+    const int full = std::min(wave_len(c), n_src);
+    for (const int div : {2, 4}) {
+        const int cap = (full + div - 1) / div;
+        if (cap < 1 || cap >= full) continue;
+        c->wave_cap = cap;
+        float ms;
+        int rc = best_time(c, 2, run, &ms);
+        if (rc) return restore(rc);
+        if (ms < best * 0.99f) {  // a clear gain only
+            best = ms;
+            bw = cap;
+        }
+    }
+    c->wave_cap = bw;
+    c->timing = keep_timing;
+    if (best_block) *best_block = bb;
+    if (best_bpc) *best_bpc = bp;
+    if (best_wave_sources) *best_wave_sources = bw;
+    if (best_ms) *best_ms = best;
+    return art_sync(c);
+}
+
+int art_autotune_adjoint(art_ctx* c, const float* n_H, const float* x_n, const double* src_pos,
+                         const float* src_lum, int n_src, float* rate, float* force, const float* g_rate,
+                         const float* g_force, float* g_nH, float* g_xn, int* best_block, int* best_bpc,
+                         float* best_ms) {
+    if (!c || n_src < 1) return ART_ERR_INVALID_ARG;
+    if (!c->o.enable_adjoint) return ART_ERR_NO_ADJOINT;
+    const bool keep_timing = c->timing;
+    c->timing = false;
+    int rc = art_trace(c, n_H, x_n, src_pos, src_lum, n_src, rate, force, nullptr);
+    c->timing = keep_timing;
+    if (rc) return rc;
+    c->timing = false;
+    uint64_t tape = 0;
+    art_get_tape(c, &tape);
+    const int keep_b = c->adj_block, keep_p = c->adj_bpc;
+    // over the stored tree when the sources fit one wave, else the full adjoint
+    auto run = [&]() {
+        return tape ? art_trace_adjoint_tape(c, tape, n_H, x_n, src_pos, src_lum, n_src, g_rate, g_force, g_nH, g_xn)
+                    : art_trace_adjoint(c, n_H, x_n, src_pos, src_lum, n_src, g_rate, g_force, g_nH, g_xn);
+    };
+    float best = 1e30f;
+    int bb = keep_b, bp = keep_p;
+    for (const auto& cd : kShapes) {
+        c->adj_block = cd[0];
+        c->adj_bpc = cd[1];
+        float ms;
+        if ((rc = best_time(c, 2, run, &ms))) {
+            c->adj_block = keep_b;
+            c->adj_bpc = keep_p;
+            c->timing = keep_timing;
+            return rc;
+        }
+        if (ms < best) {
+            best = ms;
+            bb = cd[0];
+            bp = cd[1];
+        }
+    }
+    c->adj_block = bb;
+    c->adj_bpc = bp;
     c->timing = keep_timing;
     if (best_block) *best_block = bb;
     if (best_bpc) *best_bpc = bp;
@@ -2339,6 +2436,25 @@ int art_set_launch(art_ctx* c, int block_size, int blocks_per_cu) {
         return ART_ERR_INVALID_ARG;
     c->o.block_size = block_size;
     c->o.blocks_per_cu = blocks_per_cu;
+    return ART_OK;
+}
+
+int art_set_adjoint_launch(art_ctx* c, int block_size, int blocks_per_cu) {
+    if (!c) return ART_ERR_INVALID_ARG;
+    if (block_size == 0) block_size = 64;
+    if (blocks_per_cu == 0) blocks_per_cu = 16;
+    if (block_size < 64 || block_size > 256 || (block_size % 64) || blocks_per_cu < 1 || blocks_per_cu > 64)
+        return ART_ERR_INVALID_ARG;
+    c->adj_block = block_size;
+    c->adj_bpc = blocks_per_cu;
+    return ART_OK;
+}
+
+int art_set_wave_sources(art_ctx* c, int max_sources_per_wave) {
+    if (!c || max_sources_per_wave < 0) return ART_ERR_INVALID_ARG;
+    c->wave_cap = max_sources_per_wave;
+    c->tape_ok = false;
+    c->tape_gen = 0;
     return ART_OK;
 }
 

@@ -11,10 +11,10 @@ def test_cache_helpers_round_trip(tmp_path):
     assert api.autotune_cache_path(None) is None and api.autotune_cache_path(False) is None
     assert api.autotune_cache_path(str(p)) == str(p)
     assert api.load_autotune_cache(str(p)) == {}
-    api.store_autotune_cache(str(p), "gpu|8x8x8|src1", (128, 6, 1.5))
-    api.store_autotune_cache(str(p), "gpu|8x8x8|src2", (64, 16, 2.5))
+    api.store_autotune_cache(str(p), "sweep|gpu|8x8x8|src1", (128, 6, 0, 1.5))
+    api.store_autotune_cache(str(p), "adjoint|gpu|8x8x8|src2", (64, 16, 2.5))
     data = json.loads(p.read_text())
-    assert data == {"gpu|8x8x8|src1": [128, 6, 1.5], "gpu|8x8x8|src2": [64, 16, 2.5]}
+    assert data == {"sweep|gpu|8x8x8|src1": [128, 6, 0, 1.5], "adjoint|gpu|8x8x8|src2": [64, 16, 2.5]}
     p.write_text("not json")
     assert api.load_autotune_cache(str(p)) == {}
 
@@ -38,8 +38,48 @@ def test_cached_shape_is_applied(tmp_path):
             outs.append((res, tr.trace(*args)[0].clone()))
         finally:
             tr.close()
-    (b0, p0, ms0), r0 = outs[0]
-    (b1, p1, ms1), r1 = outs[1]
-    assert (b0, p0, ms0) == (b1, p1, ms1)
-    assert list(json.loads(cache.read_text()).values()) == [[b0, p0, ms0]]
+    (b0, p0, w0, ms0), r0 = outs[0]
+    (b1, p1, w1, ms1), r1 = outs[1]
+    assert (b0, p0, w0, ms0) == (b1, p1, w1, ms1)
+    assert list(json.loads(cache.read_text()).values()) == [[b0, p0, w0, ms0]]
     assert torch.equal(r0, r1)
+
+
+@pytest.mark.gpu
+def test_tuned_settings_do_not_change_results():
+    """Whatever the autotuner picks (launch shapes of both sweeps, sources per wave),
+    fixed-point results are bitwise those of the defaults: forced caps of 1 and 2
+    sources per wave, and the tuned adjoint shape, against a default context."""
+    import torch
+    from paper_1711_06277_amd import inputs as I
+    from paper_1711_06277_amd.api import ArtTracer
+    wl = I.config(4, n_src=5, n=32)
+    args = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (wl.n_H, wl.x_n, wl.src_pos, wl.src_lum)]
+    w, v = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (wl.w, wl.v))
+    kw = dict(s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins, max_sources=wl.n_src, deterministic=True,
+              enable_adjoint=True)
+    ref = ArtTracer(wl.nx, wl.ny, wl.nz, **kw)
+    try:
+        r0 = [t.clone() for t in ref.trace(*args, want_J=True)]
+        g0 = [t.clone() for t in ref.adjoint(*args, w, v)]
+    finally:
+        ref.close()
+    tr = ArtTracer(wl.nx, wl.ny, wl.nz, **kw)
+    try:
+        for cap in (1, 2, 0):
+            tr.set_wave_sources(cap)
+            r = tr.trace(*args, want_J=True)
+            assert tr.stats(wl.n_src).n_waves == (wl.n_src if cap == 1 else 3 if cap == 2 else 1)
+            assert all(torch.equal(a, b) for a, b in zip(r, r0)), cap
+            g = tr.adjoint(*args, w, v)
+            assert all(torch.equal(a, b) for a, b in zip(g, g0)), cap
+        bb, bp, bw, ms = tr.autotune(*args)
+        assert bw in (0, 3, 2) and ms > 0
+        ab, ap, ams = tr.autotune_adjoint(*args, w, v)
+        assert ab in (64, 128, 256) and ams > 0
+        r = tr.trace(*args, want_J=True)
+        assert all(torch.equal(a, b) for a, b in zip(r, r0))
+        g = tr.adjoint(*args, w, v, tape=tr.last_tape or None)
+        assert all(torch.equal(a, b) for a, b in zip(g, g0))
+    finally:
+        tr.close()
