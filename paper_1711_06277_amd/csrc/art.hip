@@ -1290,11 +1290,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                     for (int b = 0; b < NB; ++b) {
                         const double x = dtau[b];
                         double e, om;
-                        exp_neg(x, e, om);
-                        // transmission at the segment's entry: E(out) / e^{-dtau}, or
+                        double einv;
+                        exp_neg_pos(x, e, om, einv);
+                        // transmission at the segment's entry: E(out) e^{+dtau}, or
                         // directly where either underflows
                         tau[b] -= min_f64(x, kTauStep);
-                        double Ein = E[b] * rcp_f64(e);
+                        double Ein = E[b] * einv;
                         if (!(E[b] > 1e-290 && e > 1e-290)) Ein = exp(-tau[b]);
                         E[b] = Ein;
                         const double Lin = lnom[b] * Ein;

@@ -433,35 +433,39 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
     return r;
 }
 
-// e = e^{-x} and om = 1 - e^{-x} in FP64 for x >= 0 (any size), by Cody and
-// Waite's reduction: e^{-x} = 2^{-k} e^{y}, k = rint(x / ln 2),
-// y = k ln 2 - x in [-ln2/2, ln2/2] with ln 2 in two parts (fused multiply-adds),
-// and e^{y} - 1 by its Taylor series to degree 14
-// (truncation below 1e-17 relative).  om = -(e^{y} - 1) when k = 0 (no
-// cancellation), else 1 - e >= 0.29.  x is capped at 800 (e^{-800} is 0 in
-// FP64), so k stays small and y stays in range however large x is.
-__device__ __forceinline__ void exp_neg(double x, double& e, double& om) {
+// e = e^{-x}, om = 1 - e^{-x} and einv = e^{+x} in FP64 for x >= 0, from one Cody and
+// Waite reduction: k = rint(x / ln 2), y = k ln 2 - x in [-ln2/2, ln2/2] (ln 2 in two
+// parts), e^{-x} = 2^{-k} e^{y} and e^{x} = 2^{k} e^{-y}.  e^{y} - 1 and e^{-y} - 1 share
+// the even and odd parts of the Taylor series of e^{y} - 1 to degree 11 (truncation
+// below 1e-14 relative): E(z) = z/2! + z^2/4! + ... + z^5/10!, O(z) = 1 + z/3! + ... +
+// z^5/11!, z = y^2, e^{+-y} - 1 = E +- y O.  om = -(e^{y} - 1) when k = 0 (no
+// cancellation), else 1 - e >= 0.29.  x is capped at 800; einv overflows to +inf
+// beyond x ~ 709 (callers use it only where e is normal).
+__device__ __forceinline__ void exp_neg_pos(double x, double& e, double& om, double& einv) {
     x = min_f64(x, 800.0);
     const double kd = rint(x * 1.4426950408889634);
     double y = fma(kd, 0x1.62e42feep-1, -x);
     y = fma(kd, 0x1.a39ef35793c76p-33, y);
-    double p = 1.0 / 87178291200.0;  // 1/14!
-    p = fma3(p, y, 1.0 / 6227020800.0);
-    p = fma3(p, y, 1.0 / 479001600.0);
-    p = fma3(p, y, 1.0 / 39916800.0);
-    p = fma3(p, y, 1.0 / 3628800.0);
-    p = fma3(p, y, 1.0 / 362880.0);
-    p = fma3(p, y, 1.0 / 40320.0);
-    p = fma3(p, y, 1.0 / 5040.0);
-    p = fma3(p, y, 1.0 / 720.0);
-    p = fma3(p, y, 1.0 / 120.0);
-    p = fma3(p, y, 1.0 / 24.0);
-    p = fma3(p, y, 1.0 / 6.0);
-    p = fma(p, y, 0.5);
-    p = fma(p, y, 1.0);
-    p = p * y;  // e^{y} - 1
-    e = ldexp(1.0 + p, -(int)kd);
-    om = kd == 0.0 ? -p : 1.0 - e;
+    const double z = y * y;
+    double ev = 1.0 / 3628800.0;  // 1/10!
+    ev = fma3(ev, z, 1.0 / 40320.0);
+    ev = fma3(ev, z, 1.0 / 720.0);
+    ev = fma3(ev, z, 1.0 / 24.0);
+    ev = fma(ev, z, 0.5);
+    ev = ev * z;
+    double od = 1.0 / 39916800.0;  // 1/11!
+    od = fma3(od, z, 1.0 / 362880.0);
+    od = fma3(od, z, 1.0 / 5040.0);
+    od = fma3(od, z, 1.0 / 120.0);
+    od = fma3(od, z, 1.0 / 6.0);
+    od = fma(od, z, 1.0);
+    const double yo = y * od;
+    const double pp = ev + yo;  // e^{y} - 1
+    const double pm = ev - yo;  // e^{-y} - 1
+    const int k = (int)kd;
+    e = ldexp(1.0 + pp, -k);
+    einv = ldexp(1.0 + pm, k);
+    om = kd == 0.0 ? -pp : 1.0 - e;
 }
 
 // FP64 versions for the adjoint: phi(x) = (1 - e^{-x})/x and
