@@ -95,7 +95,7 @@ typedef struct {
 typedef struct {
     int status;                    /* ART_OK or the first device-side error of the last call */
     int n_src;                     /* sources in the last art_trace */
-    int n_waves;                   /* source waves the last art_trace was split into */
+    int n_waves;                   /* source waves of the last call that traced at least one source */
     uint64_t segments;             /* ray-cell segments deposited (all sources) */
     uint64_t destroy;              /* sum over ended rays of 4^(level_max - level) */
     uint64_t destroy_expected;     /* n_src * 12 * 4^level_max */
@@ -128,7 +128,9 @@ int art_set_stream(art_ctx *ctx, void *stream);
  *   J       [n_bins][N] out (may be NULL): sum of L_in dr (1-e^{-dtau})/dtau per cell,
  *                      i.e. c E dV of Eq. e:Erad with the chi -> 0 limit taken
  * All sources share one ray pool; they are traced together in waves of as many
- * sources as the pool holds.  Asynchronous on the context's stream.
+ * sources as the pool holds: if a geometric bound shared by every source needs
+ * more than one wave, the device plans the waves from a bound on each source's
+ * own rays (no host synchronisation).  Asynchronous on the context's stream.
  * On a context with adjoint support, a trace done in one wave keeps its ray tree
  * in the pool as a tape for art_trace_adjoint_tape (see art_get_tape). */
 int art_trace(art_ctx *ctx, const float *n_H, const float *x_n, const double *src_pos,
@@ -183,11 +185,14 @@ int art_trace_and_adjoint(art_ctx *ctx, const float *n_H, const float *x_n, cons
 int art_sync(art_ctx *ctx);
 
 /* Synchronise and copy the statistics of the last art_trace (and per-source
- * arrays, each [stats_sources][ART_MAX_LEVELS] or [stats_sources][ART_MAX_BINS],
- * any of which may be NULL). */
+ * arrays, each [stats_sources][ART_MAX_LEVELS], [stats_sources][ART_MAX_BINS] or
+ * [stats_sources], any of which may be NULL).  src_rays_bound: the bound on each
+ * source's rays that planned the source waves on the device (all zero if the last
+ * call did not plan them there: one wave, or a tuned cap on sources per wave). */
 int art_get_stats(art_ctx *ctx, art_stats *out, int stats_sources, uint32_t *src_created,
                   uint32_t *src_split, uint32_t *src_exited, uint32_t *src_terminated,
-                  double *src_escaped, double *src_residual, uint64_t *src_segments);
+                  double *src_escaped, double *src_residual, uint64_t *src_segments,
+                  uint64_t *src_rays_bound);
 
 /* Autotuning (times real runs on the given inputs, synchronises; outputs hold the
  * last run).  art_autotune times the forward sweep for each launch shape of a

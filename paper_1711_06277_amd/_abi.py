@@ -90,7 +90,7 @@ def lib() -> C.CDLL:
         L.art_trace_adjoint_tape.argtypes = [vp, C.c_uint64, vp, vp, vp, vp, C.c_int, vp, vp, vp, vp]
         L.art_trace_and_adjoint.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
         L.art_sync.argtypes = [vp]
-        L.art_get_stats.argtypes = [vp, C.POINTER(art_stats), C.c_int, vp, vp, vp, vp, vp, vp, vp]
+        L.art_get_stats.argtypes = [vp, C.POINTER(art_stats), C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
         L.art_autotune.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, C.POINTER(C.c_int),
                                    C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_float)]
         L.art_autotune_adjoint.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp, vp, vp, vp,
@@ -178,10 +178,10 @@ def art_sync(ctx) -> int:
 
 
 def art_get_stats(ctx, n_src_stats, created, split, exited, terminated, escaped, residual,
-                  segments) -> art_stats:
+                  segments, rays_bound=None) -> art_stats:
     st = art_stats()
     check(lib().art_get_stats(C.c_void_p(ctx), C.byref(st), int(n_src_stats), created, split,
-                              exited, terminated, escaped, residual, segments), "art_get_stats")
+                              exited, terminated, escaped, residual, segments, rays_bound), "art_get_stats")
     return st
 
 

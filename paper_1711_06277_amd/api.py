@@ -49,6 +49,7 @@ class TraceStats:
     src_escaped: np.ndarray  # [n_src, 2]
     src_residual: np.ndarray
     src_segments: np.ndarray  # [n_src]
+    src_rays_bound: np.ndarray  # [n_src] bound on each source's rays (device-planned waves; else 0)
 
 
 class ArtTracer:
@@ -295,8 +296,9 @@ class ArtTracer:
         esc = np.zeros((ns, 2))
         res = np.zeros((ns, 2))
         seg = np.zeros(ns, dtype=np.uint64)
+        bnd = np.zeros(ns, dtype=np.uint64)
         st = A.art_get_stats(self._ctx, ns, *(arr[k].ctypes.data for k in "cset"),
-                             esc.ctypes.data, res.ctypes.data, seg.ctypes.data)
+                             esc.ctypes.data, res.ctypes.data, seg.ctypes.data, bnd.ctypes.data)
         n = min(ns, st.n_src)
         return TraceStats(
             status=st.status, n_src=st.n_src, n_waves=st.n_waves, segments=int(st.segments),
@@ -308,7 +310,7 @@ class ArtTracer:
             src_created=arr["c"][:n].astype(np.int64), src_split=arr["s"][:n].astype(np.int64),
             src_exited=arr["e"][:n].astype(np.int64), src_terminated=arr["t"][:n].astype(np.int64),
             src_escaped=esc[:n, : self.n_bins], src_residual=res[:n, : self.n_bins],
-            src_segments=seg[:n].astype(np.int64))
+            src_segments=seg[:n].astype(np.int64), src_rays_bound=bnd[:n].astype(np.int64))
 
     def autotune_key(self, n_src: int, kind: str = "sweep") -> str:
         """Cache key of a tuned setting: what is tuned ("sweep": launch shape and sources

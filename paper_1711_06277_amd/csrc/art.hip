@@ -62,7 +62,7 @@ struct CallCounters {
     unsigned long long segments;
     unsigned long long rays_wave_max;
     uint32_t status;
-    uint32_t pad;
+    uint32_t waves;               // source waves that traced at least one source
     double scale, inv_scale;      // forward fixed point: ~2^50 / L_total
     double gscale[2], inv_gscale[2];  // adjoint fixed point: dL/dn_H, dL/dx_n
 };
@@ -82,7 +82,8 @@ struct Pool {
     uint32_t* pix;    // nested pixel at the ray's level
     double* tau;      // [cap][2]: optical depth from the source at the ray's start
     uint32_t* child;  // pool index of the first of the four children (or kNoChild)
-    double* G;        // [cap][2]: adjoint, loss contributed downstream of the start
+    double* G;        // [cap][2]: adjoint, loss contributed downstream of the start; the same
+                      // memory as tau, which no adjoint reads and the next forward reseeds
     double* tend;     // [cap][2]: optical depth where a splitting ray split; -1 if it did not
     // adjoint tape (NULL without adjoint support): the cell of each ray's last
     // segment (kNoChild if it has none), that segment's upper end, and the
@@ -258,6 +259,7 @@ __global__ void k_begin_call(Counters* ct, const float* src_lum, int n_src, int 
         ct->c.segments = 0ull;
         ct->c.rays_wave_max = 0ull;
         ct->c.status = 0u;
+        ct->c.waves = 0u;
         const double margin = 1.0 + 0x1p-10;
         const double D = 4.0 * 1.7320508075688772 * Lmax / (12.0 * ldexp(1.0, 2 * level0)) * margin;
         const double S = (double)n_shell * 1.7320508075688772 * L * margin;
@@ -322,10 +324,18 @@ __global__ void k_adj_scale_final(Counters* ct, const float* src_lum, int n_lum,
 // Seed a source wave: 12*4^l0 rays per source at level l0 (Sec. 2.1), source
 // major and nested pixel minor, so that a wavefront holds 64 neighbouring
 // directions of one source.  Resets the wave counters.
-__global__ void k_seed(Pool pool, Counters* ct, int level0, int src0, int n_wave, int n_bins,
+// With a wave table (planned on the device), wave w traces sources
+// wtab[w] .. wtab[w + 1] - 1 and src0 / n_wave are ignored; past the last planned
+// wave it seeds nothing, and every later launch of the wave finds no rays.
+__global__ void k_seed(Pool pool, Counters* ct, int level0, int src0, int n_wave, const int* wtab, int w,
                        int want_child) {
     const uint32_t per_src = 12u << (2 * level0);
+    if (wtab) {
+        src0 = wtab[w];
+        n_wave = wtab[w + 1] - src0;
+    }
     const uint64_t n = (uint64_t)per_src * (uint64_t)n_wave;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n_wave > 0) atomicAdd(&ct->c.waves, 1u);
     if (blockIdx.x == 0 && threadIdx.x <= ART_MAX_LEVELS) {
         const int l = threadIdx.x;
         ct->w.head[l] = 0u;
@@ -347,7 +357,100 @@ __global__ void k_seed(Pool pool, Counters* ct, int level0, int src0, int n_wave
     for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n_tiles;
          t += (uint64_t)gridDim.x * blockDim.x)
         pool.tsum[t] = 0u;
-    (void)n_bins;
+}
+
+// ---------------------------------------------------------------------------
+// Source waves planned on the device
+// ---------------------------------------------------------------------------
+
+// Pixels of the coarse levels are tested one by one; deeper levels through
+// their level-kBoundLevel ancestors.
+constexpr int kBoundLevel = 6;
+constexpr uint32_t kDirTable = 12u * ((1u << (2 * (kBoundLevel + 1))) - 1u) / 3u;  // levels 0..kBoundLevel
+
+__host__ __device__ constexpr uint32_t dir_offset(int level) { return 12u * ((1u << (2 * level)) - 1u) / 3u; }
+
+// Unrotated HEALPix pixel centres of levels 0..kBoundLevel, level by level.
+__global__ void k_dir_table(double* dirs) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < kDirTable; i += gridDim.x * blockDim.x) {
+        int l = 0;
+        while (l < kBoundLevel && i >= dir_offset(l + 1)) ++l;
+        double v[3];
+        healpix_nest_dir(l, i - dir_offset(l), v);
+        dirs[3 * i] = v[0];
+        dirs[3 * i + 1] = v[1];
+        dirs[3 * i + 2] = v[2];
+    }
+}
+
+// An upper bound on the rays one source creates (one workgroup per source).  A
+// level-l ray exists only if its parent split, i.e. if the parent's direction
+// at r_max(l-1) is strictly inside the box (Sec. 2.1; its ancestors must have
+// split too, so counting all level-(l-1) directions is a bound).  Levels up to
+// kBoundLevel are counted pixel by pixel; a deeper level's pixels are counted
+// through their level-kBoundLevel ancestors, whose descendants' directions lie
+// within twice the mean pixel spacing sqrt(4 pi / N_pix) of the ancestor's (the
+// largest distance is about one spacing), so an ancestor counts all of them if
+// its point at r_max(l-1) is within that angle times r_max(l-1) of the box.
+// Capped by `loose`, the geometric bound the pool was sized with.
+__global__ void __launch_bounds__(256) k_src_bound(Geo g, const double* __restrict__ src_pos, int n_src,
+                                                   const double* __restrict__ dirs, int deepest,
+                                                   unsigned long long loose, unsigned long long* bound) {
+    __shared__ uint32_t part[256 / kWave];
+    const int s = blockIdx.x;
+    if (s >= n_src) return;
+    const double xs[3] = {src_pos[3 * s], src_pos[3 * s + 1], src_pos[3 * s + 2]};
+    const double hi[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
+    unsigned long long tot = 12ull << (2 * g.level0);
+    for (int l = g.level0 + 1; l <= deepest; ++l) {
+        const int L = l - 1, Lc = L < kBoundLevel ? L : kBoundLevel;
+        const double R = g.rmax[L];
+        const double spacing = sqrt(4.0 * M_PI / (double)(12u << (2 * Lc)));
+        const double pad = (L > Lc ? 2.0 * spacing * R : 0.0) + 1e-6 * (R + 1.0);
+        const uint32_t npix = 12u << (2 * Lc);
+        const double* d = dirs + 3 * (uint64_t)dir_offset(Lc);
+        uint32_t cnt = 0;
+        for (uint32_t p = threadIdx.x; p < npix; p += blockDim.x) {
+            bool in = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double u = g.rot[3 * a] * d[3 * p] + g.rot[3 * a + 1] * d[3 * p + 1] + g.rot[3 * a + 2] * d[3 * p + 2];
+                const double x = xs[a] + R * u;
+                in = in && x > -pad && x < hi[a] + pad;
+            }
+            cnt += in ? 1u : 0u;
+        }
+        cnt = wave_sum(cnt);
+        if (lane_id() == 0) part[threadIdx.x / kWave] = cnt;
+        __syncthreads();
+        unsigned long long c = 0;
+        for (int k = 0; k < (int)(blockDim.x / kWave); ++k) c += part[k];
+        __syncthreads();
+        const unsigned long long rays = 4ull * c << (2 * (L - Lc));
+        tot += rays < (12ull << (2 * l)) ? rays : (12ull << (2 * l));
+    }
+    if (threadIdx.x == 0) bound[s] = tot < loose ? tot : loose;
+}
+
+// Consecutive sources into waves whose bounds add up to at most `cap` rays (a
+// source whose bound alone exceeds it gets a wave of its own): wave w is
+// sources wtab[w] .. wtab[w + 1] - 1; entries past the last wave repeat n_src.
+// At most max_waves waves (the fixed-size plan's count, which this never exceeds
+// because every bound is at most the one that plan assumed).
+__global__ void k_plan_waves(const unsigned long long* bound, int n_src, unsigned long long cap, int max_waves,
+                             int* wtab) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int w = 0, s = 0;
+    while (s < n_src) {
+        wtab[w++] = s;
+        if (w == max_waves) {  // not reached (see above); the last wave would take the rest
+            s = n_src;
+            break;
+        }
+        unsigned long long acc = 0;
+        while (s < n_src && (acc == 0 || acc + bound[s] <= cap)) acc += bound[s++];
+    }
+    for (int k = w; k <= max_waves; ++k) wtab[k] = n_src;
 }
 
 // --------------------------------------------------------------------------
@@ -1497,6 +1600,10 @@ struct art_ctx {
     uint64_t per_src_bound;
     int wave_max;               // sources the pool holds in one wave
     int wave_cap = 0;           // at most this many sources per wave (0: wave_max)
+    double* dirs = nullptr;     // [3 * kDirTable] HEALPix centres of the coarse levels (wave planning)
+    unsigned long long* sbound = nullptr;  // [max_sources] rays bound per source of the last planned call
+    int* wtab = nullptr;        // [max_sources + 2] first source of each planned wave
+    bool last_planned = false;  // the last call planned its waves on the device
     int adj_block = 64;         // launch shape of the adjoint sweeps
     int adj_bpc = 16;
     int cur_wave = 1;           // sources in the wave being swept (sizes the shallow levels' grids)
@@ -1668,7 +1775,6 @@ void free_all(art_ctx* c) {
     (void)hipFree(c->pool.pix);
     (void)hipFree(c->pool.tau);
     (void)hipFree(c->pool.child);
-    (void)hipFree(c->pool.G);
     (void)hipFree(c->pool.last);
     (void)hipFree(c->pool.rlast);
     (void)hipFree(c->pool.taulast);
@@ -1691,6 +1797,9 @@ void free_all(art_ctx* c) {
     (void)hipFree(c->rot);
     (void)hipFree(c->q);
     (void)hipFree(c->fg);
+    (void)hipFree(c->dirs);
+    (void)hipFree(c->sbound);
+    (void)hipFree(c->wtab);
     (void)hipFree(c->wv);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->ev_call0) (void)hipEventDestroy(c->ev_call0);
@@ -1798,12 +1907,45 @@ int launch_adjoint(art_ctx* c, const AdjArgs& a, int level) {
     return ART_OK;
 }
 
-int seed_wave(art_ctx* c, int s0, int n_wave) {
+// Seed wave w: sources s0 .. s0 + n_wave - 1, or (planned) those of the device's
+// wave table, of which n_wave is then an upper bound.
+int seed_wave(art_ctx* c, int s0, int n_wave, bool planned, int w) {
     c->cur_wave = n_wave;
     const uint64_t n = (uint64_t)(12ull << (2 * c->p.level0)) * (uint64_t)n_wave;
     hipLaunchKernelGGL(k_seed, dim3(fill_blocks(n)), dim3(256), 0, c->stream, c->pool, c->ct, c->p.level0, s0,
-                       n_wave, c->p.n_bins, c->pool.child ? 1 : 0);
+                       n_wave, planned ? (const int*)c->wtab : nullptr, w, c->pool.child ? 1 : 0);
     HIP_TRY(hipGetLastError());
+    return ART_OK;
+}
+
+// Source waves of a call: as many sources per wave as the pool holds for the
+// geometric bound every source shares (or the tuned cap), or, when that takes
+// more than one wave, waves planned on the device from each source's own bound
+// (no host synchronisation: the host launches the fixed-size plan's number of
+// waves, and those the device plan does not need find no rays).  per_wave()
+// sweeps one seeded wave.  Returns the number of waves launched.
+template <class F>
+int for_waves(art_ctx* c, const double* src_pos, int n_src, int* launched, F&& per_wave) {
+    const int len = wave_len(c);
+    const int W = n_src > 0 ? (n_src + len - 1) / len : 0;
+    const bool plan = W > 1 && c->wave_cap == 0 && c->dirs;
+    c->last_planned = plan;
+    if (plan) {
+        const unsigned long long loose = c->per_src_bound;
+        hipLaunchKernelGGL(k_src_bound, dim3(n_src), dim3(256), 0, c->stream, c->geo, src_pos, n_src, c->dirs,
+                           c->deepest, loose, c->sbound);
+        hipLaunchKernelGGL(k_plan_waves, dim3(1), dim3(64), 0, c->stream, (const unsigned long long*)c->sbound,
+                           n_src, (unsigned long long)c->pool.cap, W, c->wtab);
+        HIP_TRY(hipGetLastError());
+    }
+    for (int w = 0; w < W; ++w) {
+        const int s0 = w * len;
+        const int nw = plan ? n_src : std::min(len, n_src - s0);
+        int rc = seed_wave(c, s0, nw, plan, w);
+        if (rc) return rc;
+        if ((rc = per_wave())) return rc;
+    }
+    *launched = W;
     return ART_OK;
 }
 
@@ -1897,7 +2039,8 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
         return ART_ERR_HIP;
     }
     init_geometry(c, nx, ny, nz, *params);
-    const uint64_t bytes_per_ray = 4 + 4 + 16 + 16 + (o.enable_adjoint ? 4 + 16 + 4 + 8 + 16 : 0);
+    // src, pix, tau (shared with the adjoint's G), tend; with the adjoint: child, last, rlast, taulast
+    const uint64_t bytes_per_ray = 4 + 4 + 16 + 16 + (o.enable_adjoint ? 4 + 4 + 8 + 16 : 0);
     uint64_t cap = (uint64_t)o.pool_rays;
     if (cap == 0) {
         size_t free_b = 0, total_b = 0;
@@ -1930,11 +2073,13 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
               dmalloc(&c->st.residual, ms * 2) && dmalloc(&c->st.segments, ms) && dmalloc(&c->fscratch, 64) &&
               dmalloc(&c->ion, 4) && dmalloc(&c->rot, 9);
     if (ok && o.enable_adjoint)
-        ok = dmalloc(&c->pool.child, cap) && dmalloc(&c->pool.G, 2 * cap) && dmalloc(&c->pool.last, cap) &&
+        ok = dmalloc(&c->pool.child, cap) && dmalloc(&c->pool.last, cap) &&
              dmalloc(&c->pool.rlast, cap) && dmalloc(&c->pool.taulast, 2 * cap);
+    c->pool.G = c->pool.tau;
     // one spare cell: the sweep's deposit cache flushes cells in pairs (2g, 2g + 1)
     if (ok) ok = det ? dmalloc(&c->det, 8 * (N + 1)) : dmalloc(&c->acc, 8 * (N + 1));
     if (ok) ok = dmalloc(&c->q, N) && dmalloc(&c->fg, N);
+    if (ok) ok = dmalloc(&c->dirs, 3 * (uint64_t)kDirTable) && dmalloc(&c->sbound, ms) && dmalloc(&c->wtab, ms + 2);
     if (ok && o.enable_adjoint) ok = det ? dmalloc(&c->gdet, 2 * N) : dmalloc(&c->gk, 2 * N);
     if (ok && o.enable_adjoint) ok = dmalloc(&c->wv, N);
     if (ok) {
@@ -1954,6 +2099,12 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
         return ART_ERR_HIP;
     }
     c->geo.rot = c->rot;
+    hipLaunchKernelGGL(k_dir_table, dim3(64), dim3(256), 0, c->stream, c->dirs);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return ART_ERR_HIP;
+    }
     *out = c;
     return ART_OK;
 }
@@ -1990,12 +2141,7 @@ int trace_impl(art_ctx* c, const float* n_H, const float* x_n, const double* src
     if ((rc = zero_stats(c, ms))) return rc;
     const SweepArgs a = sweep_args(c, n_H, x_n, src_pos, src_lum, force, J, n_src);
     int waves = 0;
-    for (int s0 = 0; s0 < n_src; s0 += wave_len(c)) {
-        const int nw = std::min(wave_len(c), n_src - s0);
-        if ((rc = seed_wave(c, s0, nw))) return rc;
-        if ((rc = sweep_wave(c, a, mode))) return rc;
-        ++waves;
-    }
+    if ((rc = for_waves(c, src_pos, n_src, &waves, [&]() { return sweep_wave(c, a, mode); }))) return rc;
     const dim3 fg(fill_blocks(N)), fb(256);
     if (det)
         hipLaunchKernelGGL((k_finalize<true>), fg, fb, 0, c->stream, N, c->transparent, c->acc, c->det, lpe, c->ct,
@@ -2128,14 +2274,14 @@ int art_trace_adjoint(art_ctx* c, const float* n_H, const float* x_n, const doub
     if ((rc = begin_call(c, src_lum, n_src, n_H, x_n))) return rc;
     if ((rc = zero_stats(c, (uint64_t)c->o.max_sources))) return rc;
     const SweepArgs a = sweep_args(c, n_H, x_n, src_pos, src_lum, nullptr, nullptr, n_src);
-    for (int s0 = 0; s0 < n_src; s0 += wave_len(c)) {
-        const int nw = std::min(wave_len(c), n_src - s0);
-        if ((rc = seed_wave(c, s0, nw))) return rc;
-        if ((rc = sweep_wave(c, a, 0))) return rc;
-        if ((rc = adjoint_levels(c, aa))) return rc;
-    }
+    int waves = 0;
+    rc = for_waves(c, src_pos, n_src, &waves, [&]() {
+        int r = sweep_wave(c, a, 0);
+        return r ? r : adjoint_levels(c, aa);
+    });
+    if (rc) return rc;
     c->last_nsrc = n_src;
-    c->last_waves = (n_src + wave_len(c) - 1) / wave_len(c);
+    c->last_waves = waves;
     return adjoint_epilogue(c, g_nH, g_xn);
 }
 
@@ -2181,13 +2327,11 @@ int art_trace_and_adjoint(art_ctx* c, const float* n_H, const float* x_n, const 
     // each wave's tree is walked back right after its forward sweep, while the
     // pool still holds it: no wave is traced twice
     int waves = 0;
-    for (int s0 = 0; s0 < n_src; s0 += wave_len(c)) {
-        const int nw = std::min(wave_len(c), n_src - s0);
-        if ((rc = seed_wave(c, s0, nw))) return rc;
-        if ((rc = sweep_wave(c, a, mode))) return rc;
-        if ((rc = adjoint_levels(c, aa))) return rc;
-        ++waves;
-    }
+    rc = for_waves(c, src_pos, n_src, &waves, [&]() {
+        int r = sweep_wave(c, a, mode);
+        return r ? r : adjoint_levels(c, aa);
+    });
+    if (rc) return rc;
     const dim3 fg(fill_blocks(N)), fb(256);
     if (det)
         hipLaunchKernelGGL((k_finalize<true>), fg, fb, 0, c->stream, N, c->transparent, c->acc, c->det, lpe, c->ct,
@@ -2235,14 +2379,15 @@ int art_sync(art_ctx* c) {
 }
 
 int art_get_stats(art_ctx* c, art_stats* out, int ns, uint32_t* created, uint32_t* split, uint32_t* exited,
-                  uint32_t* terminated, double* escaped, double* residual, uint64_t* segments) {
+                  uint32_t* terminated, double* escaped, double* residual, uint64_t* segments,
+                  uint64_t* rays_bound) {
     if (!c || !out) return ART_ERR_INVALID_ARG;
     HIP_TRY(hipStreamSynchronize(c->stream));
     Counters h;
     HIP_TRY(hipMemcpy(&h, c->ct, sizeof h, hipMemcpyDeviceToHost));
     memset(out, 0, sizeof *out);
     out->n_src = c->last_nsrc;
-    out->n_waves = c->last_waves;
+    out->n_waves = (int)h.c.waves;
     out->segments = h.c.segments;
     out->destroy = h.c.destroy;
     out->destroy_expected = destroy_expected(c, c->last_nsrc);
@@ -2266,6 +2411,12 @@ int art_get_stats(art_ctx* c, art_stats* out, int ns, uint32_t* created, uint32_
             if (escaped) HIP_TRY(hipMemcpy(escaped, c->st.escaped, (size_t)m * 2 * 8, hipMemcpyDeviceToHost));
             if (residual) HIP_TRY(hipMemcpy(residual, c->st.residual, (size_t)m * 2 * 8, hipMemcpyDeviceToHost));
             if (segments) HIP_TRY(hipMemcpy(segments, c->st.segments, (size_t)m * 8, hipMemcpyDeviceToHost));
+            if (rays_bound) {
+                if (c->last_planned && c->sbound)
+                    HIP_TRY(hipMemcpy(rays_bound, c->sbound, (size_t)m * 8, hipMemcpyDeviceToHost));
+                else
+                    memset(rays_bound, 0, (size_t)m * 8);
+            }
         }
     }
     return ART_OK;

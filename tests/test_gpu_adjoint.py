@@ -15,7 +15,7 @@ def adjoint_problem(n=32, n_src=3, seed=4, tau_term=I.TAU_TERM_1E10):
     return wl
 
 
-def gpu_adjoint(wl, deterministic=False, with_forward=True, **opts):
+def gpu_adjoint(wl, deterministic=False, with_forward=True, expect_waves=False, **opts):
     import torch
     from paper_1711_06277_amd.api import ArtTracer
     tr = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
@@ -35,6 +35,8 @@ def gpu_adjoint(wl, deterministic=False, with_forward=True, **opts):
             tr.trace(nH, xn, pos, lum)
             tape = tr.last_tape or None
         g_nH, g_xn = tr.adjoint(nH, xn, pos, lum, w, v, tape=tape)
+        if expect_waves:
+            assert tr.stats(wl.n_src).n_waves > 1
         return g_nH.cpu().numpy(), g_xn.cpu().numpy()
     finally:
         tr.close()
@@ -80,10 +82,12 @@ def test_adjoint_deterministic_bitwise(oracle):
 
 
 def test_adjoint_multiwave(oracle):
+    """A pool that holds about one source's tree: the adjoint retraces and walks
+    back one wave at a time (each wave's tree is gone once the next is seeded)."""
     wl = adjoint_problem(n=24, n_src=3)
     ref_nH, ref_xn = oracle.adjoint(wl.nx, wl.ny, wl.nz, wl.n_H, wl.x_n, wl.src_pos, wl.src_lum,
                                     wl.w, wl.v, **wl.params())
-    g_nH, g_xn = gpu_adjoint(wl, pool_rays=400000)
+    g_nH, g_xn = gpu_adjoint(wl, pool_rays=32000, expect_waves=True)
     compare_grad("g_nH", g_nH, ref_nH)
     compare_grad("g_xn", g_xn, ref_xn)
 
@@ -219,7 +223,7 @@ def test_tape_is_refused_when_stale():
     finally:
         tr.close()
     tm = ArtTracer(wl.nx, wl.ny, wl.nz, s_H=wl.s_H, s_d=wl.s_d, n_bins=wl.n_bins,
-                   max_sources=wl.n_src, enable_adjoint=True, pool_rays=300000)
+                   max_sources=wl.n_src, enable_adjoint=True, pool_rays=30000)
     try:
         tm.trace(*args)
         assert tm.stats(wl.n_src).n_waves > 1 and tm.last_tape == 0

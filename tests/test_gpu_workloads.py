@@ -136,7 +136,9 @@ def test_workload5_full_size_against_oracle(wl5):
     holds (source 0 and the brightest) have the oracle's ray tree bit for bit and
     its escaped / residual luminosity; and the batch equals the sum of 64 calls of
     16 sources cell by cell (rate, J, |F|), which pins the fixed-point resolution
-    at this workload's luminosity range."""
+    at this workload's luminosity range.  The sources' waves are planned on the
+    device from a bound on each source's rays: it holds for every source, and the
+    1024 sources fit in a few waves."""
     wl = wl5
     with open(GOLDEN5) as f:
         gold = json.load(f)
@@ -146,8 +148,13 @@ def test_workload5_full_size_against_oracle(wl5):
     try:
         rate, force, J = tr.trace(nH, xn, pos, lum, want_J=True)
         st = tr.stats(wl.n_src)
-        print(f"\n{st.segments} segments in {st.n_waves} waves, rays in the largest wave {st.rays_max_wave}")
+        per_src = st.src_created.sum(axis=1)
+        print(f"\n{st.segments} segments in {st.n_waves} waves, rays in the largest wave {st.rays_max_wave}; "
+              f"per-source ray bound / rays: median {np.median(st.src_rays_bound / per_src):.2f}, "
+              f"max {np.max(st.src_rays_bound / per_src):.2f}")
         assert st.status == 0 and st.destroy == st.destroy_expected
+        # the waves are planned on the device from each source's bound, which holds
+        assert np.all(st.src_rays_bound >= per_src) and st.n_waves <= 6
         cons = conservation(wl, J.cpu().numpy(), st)
         assert max(cons) <= CONS_TOL, cons
         for g in gold["sources"]:
