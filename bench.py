@@ -228,6 +228,7 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
 
     import torch
+    from paper_1711_06277_amd import _abi as A
     from paper_1711_06277_amd.api import ArtTracer
 
     if not torch.cuda.is_available():
@@ -514,8 +515,14 @@ def main():
         t5 = time.time()
         c5 = I.config(5)
         log(f"[bench] workload {c5.name}: generated in {time.time() - t5:.1f}s")
+        # a pool of 80% of the free HBM (72 bytes per ray with the adjoint's tape), and the
+        # launch shapes tuned on the 256^3 workload (the same kernels)
         tr5 = ArtTracer(c5.nx, c5.ny, c5.nz, s_H=c5.s_H, s_d=c5.s_d, n_bins=c5.n_bins, deterministic=True,
-                        max_sources=c5.n_src, enable_adjoint=True, device=dev)
+                        max_sources=c5.n_src, enable_adjoint=True, pool_mem_fraction=0.8, device=dev)
+        if tuned is not None:
+            A.art_set_launch(tr5._ctx, tuned["block_size"], tuned["blocks_per_cu"])
+            if "adjoint" in tuned:
+                A.art_set_adjoint_launch(tr5._ctx, tuned["adjoint"]["block_size"], tuned["adjoint"]["blocks_per_cu"])
         a5 = [torch.from_numpy(x).to(dev) for x in (c5.n_H, c5.x_n, c5.src_pos, c5.src_lum, c5.w, c5.v)]
         N5 = c5.n_cells
         o5 = (torch.empty(N5, device=dev), torch.empty((3, N5), device=dev), None,
