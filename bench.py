@@ -533,6 +533,18 @@ def main():
 
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
+        # the forward trace alone, once (eager)
+        torch.cuda.synchronize()
+        tf = time.perf_counter()
+        with torch.cuda.stream(side):
+            tr5.trace(*a5[:4], out=(o5[0], o5[1], None), check=False)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        t_fwd5 = time.perf_counter() - tf
+        rcf5 = tr5.sync()
+        st5f = tr5.stats(c5.n_src)
+        log(f"[bench] workload 5 eager forward: {t_fwd5:.2f} s, {st5f.segments} segments, "
+            f"{st5f.n_waves} waves, status {rcf5}")
         torch.cuda.synchronize()
         te = time.perf_counter()
         with torch.cuda.stream(side):
@@ -559,6 +571,8 @@ def main():
         tr5.close()
         w5 = {"workload": c5.name, "grid": [c5.nx, c5.ny, c5.nz], "n_sources": c5.n_src,
               "segments_per_pass": st5.segments, "waves": st5.n_waves, "rays_max_wave": st5.rays_max_wave,
+              "s_forward_eager": t_fwd5, "waves_forward": st5f.n_waves,
+              "segments_per_s_forward": st5f.segments / t_fwd5, "status_forward": rcf5,
               "s_forward_adjoint_eager": t_eager5, "s_forward_adjoint_graph_replay": t_graph5,
               "segments_per_s_forward_plus_adjoint": 2 * st5.segments / t_graph5,
               "graph_bitwise_equal_to_eager": same5, "status": rc5}
