@@ -391,7 +391,11 @@ __device__ __forceinline__ bool back_step(const Geo& g, const float2* __restrict
     for (int a = 0; a < 3; ++a) {
         const bool s2 = adv & st[a];
         m.cell[a] = s2 ? nc[a] : m.cell[a];
-        m.tprev[a] = s2 ? entry_face(r, a, nc[a]) : m.tprev[a];
+        // entry_face() without its branches: an axis with n_a = 0 never steps
+        // (its entry parameter stays -inf, below the others), so the value
+        // computed for it here is never selected
+        const double ef = ((double)(r.n[a] > 0.0 ? nc[a] : nc[a] + 1) - r.xs[a]) * r.inv[a];
+        m.tprev[a] = s2 ? ef : m.tprev[a];
     }
     m.rhi = adv ? lo0 : m.rhi;
     *stuck = *stuck | (alive & (!budget | (go & (!moved | out))));

@@ -21,6 +21,7 @@ from tests.gpu_common import CONS_TOL, compare_cells, compare_force, conservatio
 pytestmark = pytest.mark.gpu
 
 GOLDEN5 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "workload5_sources.json")
+GOLDEN4_FD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "workload4_fd.json")
 
 
 def tracer(wl, **kw):
@@ -107,7 +108,9 @@ def adj4(oracle):
 @pytest.mark.parametrize("deterministic", [False, True], ids=["fp64_accumulator", "fixed_point"])
 def test_workload4_adjoint_full_size(adj4, deterministic):
     """128^3, sigmoid x_n, 8 sources: GPU adjoint (over the stored tree, as the
-    benchmark runs it) vs the FP64 oracle adjoint, in both accumulator modes."""
+    benchmark runs it) vs the FP64 oracle adjoint on every cell, and vs central
+    finite differences of the oracle's forward sweep (relative step 1e-3) at 64
+    random cells, in both accumulator modes."""
     wl, (ref_nH, ref_xn) = adj4
     tr = tracer(wl, max_sources=wl.n_src, enable_adjoint=True, deterministic=deterministic)
     try:
@@ -117,12 +120,26 @@ def test_workload4_adjoint_full_size(adj4, deterministic):
         g_nH, g_xn = tr.adjoint(*args, dev(wl.w), dev(wl.v), tape=tr.last_tape)
     finally:
         tr.close()
+    with open(GOLDEN4_FD) as f:
+        fd = json.load(f)
+    cells = np.asarray(fd["cells"])
     for name, gpu, ref in (("g_nH", g_nH, ref_nH), ("g_xn", g_xn, ref_xn)):
         gpu = gpu.cpu().numpy().astype(np.float64)
-        m = np.abs(ref) > 1e-6 * np.abs(ref).max()
+        gmax = np.abs(ref).max()
+        m = np.abs(ref) > 1e-6 * gmax
         err = np.abs(gpu[m] - ref[m]) / np.abs(ref[m])
         print(f"\n{name}: max rel err {err.max():.2e} over {m.sum()} cells")
         assert err.max() <= 1e-4, f"{name}: {err.max():.3e}"
+        # central differences: the relative bar above the same floor, an
+        # absolute one (1e-4 of the floor) below it
+        fdv = np.asarray(fd["fd_" + name])
+        d = np.abs(gpu[cells] - fdv)
+        big = np.abs(fdv) > 1e-6 * gmax
+        rel = d[big] / np.abs(fdv[big])
+        print(f"{name} vs central differences: {big.sum()} cells at max rel err {rel.max():.2e}, "
+              f"{(~big).sum()} below the floor at max abs err {d[~big].max(initial=0.0) / gmax:.2e} of max|g|")
+        assert rel.max() <= 1e-4, f"{name} vs FD: {rel.max():.3e}"
+        assert d[~big].max(initial=0.0) <= 1e-10 * gmax, f"{name} vs FD below the floor"
 
 
 @pytest.fixture(scope="module")
