@@ -136,6 +136,27 @@ def roofline(kernel_s, segments, bytes_per_segment, traffic_bytes, valu_insts, k
             "kernel": kernel, "hbm_model": hbm, "valu_issue": valu}
 
 
+def copy_bandwidth_gbs(dev, mib=2048, repeats=5):
+    """Median rate of a device-to-device copy of ``mib`` MiB, counting the bytes
+    read and the bytes written."""
+    import numpy as np
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    del a, b
+    return 2 * n * 4 / float(np.median(ts)) / 1e9
+
+
 _BASELINE_WL = None  # the workload, inherited by the forked workers
 
 
@@ -313,8 +334,11 @@ def main():
                  "bytes_per_segment_with_accumulator_width":
                      BYTES_PER_SEGMENT_FIXED_POINT if wl.deterministic else BYTES_PER_SEGMENT,
                  "sweep_ms_per_step": sweep_ms / args.steps, "avg_launch_ms": avg_launch_ms})
+    # what a plain device copy reaches on this GPU (bytes read + written per
+    # second, median of 5): the achievable HBM rate beside the published peak
+    roof["hbm_model"]["copy_GBs"] = copy_bandwidth_gbs(dev)
     log(f"[bench] roofline: bound {roof['bound']}, frac {roof['frac']:.3f}; HBM model "
-        f"{roof['hbm_model']['frac']:.3f}")
+        f"{roof['hbm_model']['frac']:.3f}; device copy {roof['hbm_model']['copy_GBs']:.0f} GB/s")
 
     # ---- plain: one source per call, same kernel and parameters ----
     plain = None
