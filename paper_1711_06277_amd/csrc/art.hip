@@ -855,6 +855,12 @@ __device__ __forceinline__ void quad_combine(int lane, uint32_t& key, float (&v)
 // takes base + l.  The order matters: the quad pre-combine pairs sibling rays
 // (four consecutive rays of a level) by lane.  Every lane of the wavefront must
 // be present.
+// Largest ray pool: pool indices, child links and the per-level claim counters
+// are 32-bit, and a counter overshoots its level's end by one 64-ray claim per
+// wavefront of the launch (at most 64 workgroups of 4 wavefronts per CU: 2^22
+// rays on 256 CUs), so with 2^23 rays of room it never wraps.
+constexpr uint64_t kMaxPoolRays = 0xff800000ull;
+
 __device__ __forceinline__ uint32_t claim_rays(uint32_t* head, int lane) {
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(head, (uint32_t)kWave);
@@ -2052,7 +2058,7 @@ int art_create(art_ctx** out, int nx, int ny, int nz, const art_params* params, 
         const uint64_t fits = (uint64_t)((double)free_b * o.pool_mem_fraction) / bytes_per_ray;
         cap = std::min(want, fits);
     }
-    cap = std::min<uint64_t>(cap, 0xfffffff0ull);
+    cap = std::min<uint64_t>(cap, kMaxPoolRays);
     const uint64_t seeds = 12ull << (2 * params->level0);
     if (cap < seeds) {
         delete c;
@@ -2775,7 +2781,7 @@ bool noalloc_layout(art_ctx* c, unsigned char* base, int n_src, bool want_J) {
     // the pool: 40 bytes per ray plus a tile count per kSplitTile rays, and padding
     const uint64_t room = kScratchBytes - cv.used - 5 * 256;
     uint64_t cap = (room - 8) / (40 + 1);
-    cap = std::min<uint64_t>(cap, 0xfffffff0ull);
+    cap = std::min<uint64_t>(cap, kMaxPoolRays);
     c->pool.tsum = cv.take<uint32_t>((cap + kSplitTile - 1) / kSplitTile + 1);
     c->pool.tau = cv.take<double>(2 * cap);
     c->pool.tend = cv.take<double>(2 * cap);
