@@ -84,7 +84,8 @@ typedef struct {
 typedef struct {
     int max_sources;         /* largest n_src accepted by art_trace */
     int enable_adjoint;      /* 1: also allocate the adjoint workspace */
-    int64_t pool_rays;       /* ray-pool capacity (rays per source wave); 0 = size automatically */
+    int64_t pool_rays;       /* ray-pool capacity (rays per source wave, at most 2^32 - 2^23;
+                                larger values are reduced to that); 0 = size automatically */
     double pool_mem_fraction;/* automatic sizing: at most this fraction of free HBM (0 -> 0.5) */
     int block_size;          /* threads per workgroup of the sweep kernels (64, 128, 192 or 256; 0 -> 64) */
     int blocks_per_cu;       /* workgroups per CU launched for each sweep (0 -> 16) */
