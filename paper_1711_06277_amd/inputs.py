@@ -161,7 +161,7 @@ def uniform_workload(n: int, src_pos, lum=1.0, s_H=0.05, s_d=0.0, n_H=1.0, x_n=1
     return Workload(name=f"uniform{n}", nx=n, ny=n, nz=n,
                     n_H=np.full(n ** 3, n_H, dtype=np.float32),
                     x_n=np.full(n ** 3, x_n, dtype=np.float32),
-                    src_pos=src_pos, src_lum=np.ascontiguousarray(lum, dtype=np.float32),
+                    src_pos=src_pos, src_lum=np.array(lum, dtype=np.float32),
                     s_H=s_H, s_d=s_d, n_bins=n_bins, **kw)
 
 
