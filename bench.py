@@ -111,11 +111,13 @@ def measured_adjoint_valu(workload: int, deterministic: bool):
     return _summary_value("k_adjoint_c3_sq_counters.md", "valu_insts_per_adjoint")
 
 
-def roofline(kernel_s, segments, bytes_per_segment, traffic_bytes, valu_insts, kernel, traffic_unit):
+def roofline(kernel_s, segments, bytes_per_segment, traffic_bytes, valu_insts, kernel, traffic_unit, launches):
     """The roofline block of a kernel: the method's bytes against HBM, the
     measured HBM traffic, and the measured VALU issue against the chip's issue
     rate.  The bound is whichever measured resource is busiest (HBM traffic or
-    VALU issue); its figures are the top-level achieved / peak / frac."""
+    VALU issue); its figures are the top-level achieved / peak / frac.  The
+    kernel runs as `launches` launches per pass (one per HEALPix level), and
+    `traffic` is the measured HBM bytes of an average launch (GB)."""
     model_gbs = segments * bytes_per_segment / kernel_s / 1e9
     hbm = {"achieved": model_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": model_gbs / HBM_PEAK_GBS,
            "bytes_per_segment": bytes_per_segment,
@@ -130,9 +132,13 @@ def roofline(kernel_s, segments, bytes_per_segment, traffic_bytes, valu_insts, k
     if valu is not None and (hbm["measured_frac"] is None or valu["frac"] > hbm["measured_frac"]):
         bound = "alu"
     top = valu if bound == "alu" else hbm
+    n = max(1, launches)
     return {"bound": bound, "achieved": top["achieved"], "peak": top["peak"],
             "unit": "TOP/s" if bound == "alu" else "GB/s", "frac": top["frac"],
-            "traffic": None if traffic_bytes is None else traffic_bytes / 1e9, "traffic_unit": traffic_unit,
+            "traffic": None if traffic_bytes is None else traffic_bytes / n / 1e9, "traffic_unit": traffic_unit,
+            "traffic_per_pass": None if traffic_bytes is None else traffic_bytes / 1e9,
+            "launches_per_pass": launches,
+            "algorithmic_bytes_per_launch": segments * bytes_per_segment / n,
             "kernel": kernel, "hbm_model": hbm, "valu_issue": valu}
 
 
@@ -325,11 +331,13 @@ def main():
     # the library's stream), summed over a trace
     sweep_s = sweep_ms / 1e3 / args.steps
     avg_launch_ms = sweep_ms / max(1, sweep_launches)
+    n_launch_levels = sweep_launches // max(1, args.steps)  # levels launched per trace (and per adjoint)
     roof = roofline(sweep_s, segments, BYTES_PER_SEGMENT, measured_traffic(args.workload, wl.deterministic),
                     measured_valu(args.workload, wl.deterministic),
                     "k_sweep (one launch per HEALPix level)",
-                    "GB per trace (sum over the per-level k_sweep launches), rocprofv3 FETCH_SIZE + "
-                    "WRITE_SIZE, copy-calibrated")
+                    "GB per k_sweep launch (the average of one trace's per-level launches; traffic_per_pass "
+                    "is their sum), rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated",
+                    n_launch_levels)
     roof.update({"bytes_per_segment": BYTES_PER_SEGMENT,
                  "bytes_per_segment_with_accumulator_width":
                      BYTES_PER_SEGMENT_FIXED_POINT if wl.deterministic else BYTES_PER_SEGMENT,
@@ -446,8 +454,9 @@ def main():
                             measured_adjoint_traffic(args.workload, wl.deterministic),
                             measured_adjoint_valu(args.workload, wl.deterministic),
                             "k_adjoint (one launch per level, deepest first; one backward walk over every segment)",
-                            "GB per adjoint sweep (sum over the per-level k_adjoint launches), rocprofv3 "
-                            "FETCH_SIZE + WRITE_SIZE, copy-calibrated")
+                            "GB per k_adjoint launch (the average of one adjoint's per-level launches; "
+                            "traffic_per_pass is their sum), rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated",
+                            n_launch_levels)
         adj_roof["bytes_per_segment"] = ADJOINT_BYTES_PER_SEGMENT
         adjoint = {"ms_per_adjoint": 1e3 * adj_s,
                    "ms_per_forward_with_tree": 1e3 * t_fwd / args.steps,

@@ -66,3 +66,24 @@ def test_committed_summaries_are_readable():
         with open(os.path.join(bench.ROOT, "profiles", name)) as fh:
             text = fh.read()
         assert key in text and "kernel_sources_sha:" in text
+
+
+def test_roofline_picks_the_busiest_measured_resource():
+    """VALU issue above the measured HBM fraction names the bound "alu"; traffic
+    is reported per launch (the pass's sum divided by its launches)."""
+    seg, t = 1.0e10, 0.1
+    valu = 0.6 * bench.VALU_PEAK_WAVE_INSTS * t  # 60% of the issue rate
+    r = bench.roofline(t, seg, 40, 2.0e11, valu, "k", "GB per launch", 8)
+    assert r["bound"] == "alu" and r["unit"] == "TOP/s"
+    assert r["frac"] == pytest.approx(0.6)
+    assert r["traffic"] == pytest.approx(2.0e11 / 8 / 1e9)
+    assert r["traffic_per_pass"] == pytest.approx(200.0)
+    assert r["algorithmic_bytes_per_launch"] == pytest.approx(seg * 40 / 8)
+    assert r["hbm_model"]["frac"] == pytest.approx(seg * 40 / t / 1e9 / bench.HBM_PEAK_GBS)
+    # measured traffic busier than the VALU: "hbm", with the model's figures on top
+    r = bench.roofline(t, seg, 40, 0.7 * bench.HBM_PEAK_GBS * 1e9 * t, valu, "k", "u", 8)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert r["frac"] == pytest.approx(r["hbm_model"]["frac"])
+    # no counters: HBM model only, traffic unknown
+    r = bench.roofline(t, seg, 40, None, None, "k", "u", 8)
+    assert r["bound"] == "hbm" and r["traffic"] is None and r["valu_issue"] is None
