@@ -55,6 +55,26 @@ MUTATIONS = [
      "    return nH[c] * P->s_d;\n}",
      "    return nH[c] * (xn[c] * P->s_H + P->s_d);\n}",
      phys.test_termination_every_bin),
+    # Sec. 2.1: an escaping packet counted at its launch luminosity, not attenuated
+    ("escaped_unattenuated",
+     "const double Lleft = Lnom[q] * exp(-tau[q]);",
+     "const double Lleft = Lnom[q];",
+     lambda O: phys.test_photon_conservation(O, 3.0)),
+    # Sec. 2.2 destroy counter: an ended ray weighted as one of the level below
+    ("destroy_weight",
+     "st->destroy += (uint64_t)1 << (2 * (P->level_max - l));",
+     "st->destroy += (uint64_t)1 << (2 * (P->level_max - l - 1));",
+     lambda O: phys.test_destroy_counter_total(O, 0)),
+    # Eq. e:photrate2: the rate without the neutral fraction (n_H instead of n_HI)
+    ("rate_without_xn",
+     "for (int64_t c = 0; c < N; ++c) rate[c] = P->s_H * xn[c] * nH[c] * Jw[c];",
+     "for (int64_t c = 0; c < N; ++c) rate[c] = P->s_H * nH[c] * Jw[c];",
+     phys.test_rate_counts_every_gas_absorption),
+    # adjoint chain rule: d kappa_i / d x_n taken as n_H (s_H + s_d)
+    ("adjoint_chain_xn",
+     "g_xn[c] = gk[c] * nH[c] * P->s_H + w[c] * P->s_H * nH[c] * J[c];",
+     "g_xn[c] = gk[c] * nH[c] * (P->s_H + P->s_d) + w[c] * P->s_H * nH[c] * J[c];",
+     phys.test_adjoint_vs_central_differences),
     # Sec. 2.2 Step 1: seeds injected face by face instead of interleaved
     ("seed_order_by_face",
      "r.pix = (k % 12) * per_face + k / 12;",

@@ -130,6 +130,28 @@ def test_estimator_consistency(oracle):
     assert np.allclose(res.rate, wl.s_H * xn * nH * res.J[0], rtol=1e-14, atol=0)
 
 
+def test_rate_counts_every_gas_absorption(oracle):
+    """Without dust every ionizing photon absorbed is absorbed by neutral
+    hydrogen and makes one photoionization (Eq. e:photrate2 with chi_i = n_HI
+    sigma_H): the summed rate equals emitted - escaped - residual, for any
+    neutral fraction field, here x_n uniform in (0, 1) and some x_n = 0 cells."""
+    n = 16
+    rng = np.random.default_rng(21)
+    n_H = I.lognormal_density(n, 1.0, 21)
+    x_n = rng.uniform(0.0, 1.0, n ** 3).astype(np.float32)
+    x_n[rng.choice(n ** 3, 200, replace=False)] = 0.0
+    pos = I.sample_sources(n_H, n, 2, rng)
+    lum = np.array([[3.0], [0.5]], dtype=np.float32)
+    for tau_term in (math.log(1e10), 2.0):
+        wl = I.Workload(name="dust-free", nx=n, ny=n, nz=n, n_H=n_H, x_n=x_n, src_pos=pos, src_lum=lum,
+                        s_H=0.4, s_d=0.0, n_bins=1, tau_term=tau_term)
+        res = oracle.trace_workload(wl)
+        gas = float((res.emitted[:, 0] - res.escaped[:, 0] - res.residual[:, 0]).sum())
+        assert gas > 0.1 * float(lum.sum())
+        assert res.rate.sum() == pytest.approx(gas, rel=1e-12)
+        assert (res.rate[x_n == 0] == 0).all()
+
+
 def test_uniform_medium_escape_closed_form(oracle):
     """Uniform chi: along every ray tau(r) = chi r, so the luminosity leaving the
     domain is sum over the leaf rays of L / N_ray(l) * exp(-chi max(r_a, d_exit)),
