@@ -95,3 +95,29 @@ def test_noalloc_rejects_inputs_beyond_its_workspace():
     with pytest.raises(A.ArtError) as e:  # null fields
         A.art_trace_noalloc(8, 8, 8, p, None, fake, fake, fake, 1, fake, fake, None, None, 0)
     assert e.value.code == A.ART_ERR_INVALID_ARG
+
+
+def test_c_program_links_and_calls_the_library():
+    """A C99 program that includes the header, takes the address of every
+    declared function, links against libart.so and calls art_strerror: the ABI
+    is usable from C without Python (no GPU call is made)."""
+    import tempfile
+    from paper_1711_06277_amd import _abi as A
+    names = declared_functions()
+    src = ['#include "art.h"', "#include <stdio.h>", "#include <string.h>", "typedef void (*fn)(void);",
+           "int main(void) {", "    fn all[] = {"]
+    src += [f"        (fn){n}," for n in names]
+    src += ["    };", "    for (unsigned i = 0; i < sizeof all / sizeof all[0]; ++i) if (!all[i]) return 1;",
+            '    printf("%s|%s\\n", art_strerror(ART_ERR_QUEUE_OVERFLOW), art_strerror(ART_OK));',
+            "    return 0;", "}"]
+    libdir = os.path.dirname(A.LIB_PATH)
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "use_art.c")
+        exe = os.path.join(d, "use_art")
+        open(c, "w").write("\n".join(src) + "\n")
+        subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-Wno-cast-function-type",
+                               "-I", os.path.join(ROOT, "include"), "-o", exe, c,
+                               "-L", libdir, "-l:" + os.path.basename(A.LIB_PATH),
+                               "-Wl,-rpath," + libdir, "-Wl,-rpath-link,/opt/rocm/lib"])
+        out = subprocess.check_output([exe], text=True).strip()
+    assert out == f"{A.strerror(A.ART_ERR_QUEUE_OVERFLOW)}|ok"
