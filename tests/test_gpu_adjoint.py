@@ -61,6 +61,21 @@ def test_adjoint_vs_oracle(oracle, with_forward):
     print(f"\nadjoint max rel err: g_nH {e1:.2e}, g_xn {e2:.2e}")
 
 
+@pytest.mark.parametrize("level0", [0, 4])
+@pytest.mark.parametrize("deterministic", [False, True], ids=["fp64_accumulator", "fixed_point"])
+def test_adjoint_other_start_levels(oracle, level0, deterministic):
+    """Start levels 0 (12 rays per source) and 4 (the paper's fiducial 768), both
+    accumulator modes."""
+    wl = adjoint_problem(n=28, n_src=2, seed=6)
+    wl.level0 = level0
+    ref_nH, ref_xn = oracle.adjoint(wl.nx, wl.ny, wl.nz, wl.n_H, wl.x_n, wl.src_pos, wl.src_lum,
+                                    wl.w, wl.v, **wl.params())
+    g_nH, g_xn = gpu_adjoint(wl, deterministic=deterministic)
+    e1 = compare_grad("g_nH", g_nH, ref_nH)
+    e2 = compare_grad("g_xn", g_xn, ref_xn)
+    print(f"\nlevel0 {level0}: adjoint max rel err g_nH {e1:.2e}, g_xn {e2:.2e}")
+
+
 def test_adjoint_with_terminations(oracle):
     wl = adjoint_problem(n=28, n_src=2, seed=7, tau_term=3.0)
     ref_nH, ref_xn = oracle.adjoint(wl.nx, wl.ny, wl.nz, wl.n_H, wl.x_n, wl.src_pos, wl.src_lum,

@@ -206,6 +206,19 @@ def test_level0_equals_level_max(oracle):
     check_against_oracle(oracle, wl)
 
 
+@pytest.mark.parametrize("level0", [0, 1, 4])
+@pytest.mark.parametrize("deterministic", [True, False], ids=["fixed_point", "fp32_atomic"])
+def test_other_start_levels(oracle, level0, deterministic):
+    """The paper's fiducial start level 4 (768 rays per source), and 12 or 48
+    rays per source (level 0 or 1, where a deposit can carry a twelfth of a
+    source's luminosity and the fixed-point scale is set by that bound) in a
+    turbulent two-bin medium, both deposit modes."""
+    wl = small_lognormal(nx=36, ny=30, nz=34, n_src=3, seed=31)
+    wl.level0 = level0
+    wl.deterministic = deterministic
+    check_against_oracle(oracle, wl)
+
+
 def test_vacuum(oracle):
     """s_H = s_d = 0: nothing absorbed, J follows the oracle (1/r^2 law)."""
     wl = I.uniform_workload(32, [15.2, 17.9, 16.4], lum=1.0, s_H=0.0, s_d=0.0, n_bins=1,
