@@ -219,6 +219,18 @@ def test_other_start_levels(oracle, level0, deterministic):
     check_against_oracle(oracle, wl)
 
 
+@pytest.mark.parametrize("deterministic", [True, False], ids=["fixed_point", "fp32_atomic"])
+def test_level_max_caps_splitting(oracle, deterministic):
+    """level_max = 4 below the deepest level the grid allows: level-4 rays march
+    on unsplit to the boundary (long rays, sparse far from the sources), and the
+    destroy weights are 4^(level_max - l)."""
+    wl = small_lognormal(nx=48, ny=44, nz=40, n_src=3, seed=33)
+    wl.level_max = 4
+    wl.deterministic = deterministic
+    ref, _, st = check_against_oracle(oracle, wl)
+    assert ref.split[:, 4].sum() == 0 and ref.created[:, 4].sum() > 0
+
+
 def test_vacuum(oracle):
     """s_H = s_d = 0: nothing absorbed, J follows the oracle (1/r^2 law)."""
     wl = I.uniform_workload(32, [15.2, 17.9, 16.4], lum=1.0, s_H=0.0, s_d=0.0, n_bins=1,
