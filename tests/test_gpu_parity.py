@@ -17,7 +17,7 @@ from tests.gpu_common import (CELL_FLOOR, CONS_TOL, compare_cells, compare_force
 pytestmark = pytest.mark.gpu
 
 
-def check_against_oracle(oracle, wl, **opts):
+def check_against_oracle(oracle, wl, seg_tol=1e-4, **opts):
     ref = oracle.trace_workload(wl)
     (rate, force, J), st = run_gpu(wl, want_J=True, **opts)
     assert st.status == 0, f"device status {st.status}"
@@ -35,7 +35,7 @@ def check_against_oracle(oracle, wl, **opts):
     np.testing.assert_allclose(st.src_escaped, ref.escaped, rtol=1e-5, atol=1e-12 * L_tot)
     np.testing.assert_allclose(st.src_residual, ref.residual, rtol=1e-4, atol=1e-12 * L_tot)
     seg_ratio = st.segments / max(1, int(ref.segments.sum()))
-    assert abs(seg_ratio - 1) < 1e-4, f"segment count {st.segments} vs oracle {ref.segments.sum()}"
+    assert abs(seg_ratio - 1) < seg_tol, f"segment count {st.segments} vs oracle {ref.segments.sum()}"
     print(f"\n{wl.name}: rate err {e_rate:.2e}, force err {e_force}, conservation {cons}, "
           f"segments {st.segments}")
     return ref, (rate, force, J), st
@@ -229,6 +229,23 @@ def test_level_max_caps_splitting(oracle, deterministic):
     wl.deterministic = deterministic
     ref, _, st = check_against_oracle(oracle, wl)
     assert ref.split[:, 4].sum() == 0 and ref.created[:, 4].sum() > 0
+
+
+@pytest.mark.parametrize("deterministic", [True, False], ids=["fixed_point", "fp32_atomic"])
+def test_sources_on_cell_corners_and_faces(oracle, deterministic):
+    """Sources at a cell corner, on a face and on an edge of the grid's cells
+    (integer coordinates): HEALPix directions in the coordinate planes and
+    along the diagonals then hit faces, edges and corners exactly, where axes
+    step together and segments of zero length are skipped.  The tree must
+    still match bit for bit.  The segment counts may not: the kernel takes a
+    face's parameter as (face - x_s) times 1/n_a, the oracle divides by n_a, so
+    where one sees two faces at exactly the same distance the other can see a
+    segment of a few ulps between them (0.013% more segments in the oracle
+    here, with no effect on any cell beyond rounding)."""
+    wl = small_lognormal(nx=32, ny=32, nz=32, n_src=3, seed=34)
+    wl.src_pos = np.array([[16.0, 16.0, 16.0], [10.5, 20.0, 12.5], [7.0, 7.0, 25.5]])
+    wl.deterministic = deterministic
+    check_against_oracle(oracle, wl, seg_tol=1e-3)
 
 
 def test_vacuum(oracle):
