@@ -248,6 +248,18 @@ def test_sources_on_cell_corners_and_faces(oracle, deterministic):
     check_against_oracle(oracle, wl, seg_tol=1e-3)
 
 
+@pytest.mark.parametrize("deterministic", [True, False], ids=["fixed_point", "fp32_atomic"])
+def test_sources_on_the_domain_boundary(oracle, deterministic):
+    """Sources at the domain's lower corner, on its faces and a hair inside its
+    upper faces: rays pointing out start outside (d_exit = 0) and are created and
+    exit with no segment; the rest sweep the whole box."""
+    wl = small_lognormal(nx=30, ny=26, nz=28, n_src=3, seed=35)
+    wl.src_pos = np.array([[0.0, 0.0, 0.0], [15.3, 0.0, 27.999999], [29.9999999, 12.7, 0.0]])
+    wl.deterministic = deterministic
+    ref, _, st = check_against_oracle(oracle, wl, seg_tol=1e-3)
+    assert ref.exited[:, wl.level0].sum() > 0
+
+
 def test_vacuum(oracle):
     """s_H = s_d = 0: nothing absorbed, J follows the oracle (1/r^2 law)."""
     wl = I.uniform_workload(32, [15.2, 17.9, 16.4], lum=1.0, s_H=0.0, s_d=0.0, n_bins=1,
