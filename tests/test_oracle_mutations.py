@@ -6,6 +6,7 @@ import os
 
 import pytest
 
+from tests import test_oracle_healpix as hp
 from tests import test_oracle_physics as phys
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "art_oracle.c")
@@ -75,6 +76,21 @@ MUTATIONS = [
      "g_xn[c] = gk[c] * nH[c] * P->s_H + w[c] * P->s_H * nH[c] * J[c];",
      "g_xn[c] = gk[c] * nH[c] * (P->s_H + P->s_d) + w[c] * P->s_H * nH[c] * J[c];",
      phys.test_adjoint_vs_central_differences),
+    # Sec. 2.1: the split radius with pi m_ray replaced by 2 pi m_ray
+    ("split_radius",
+     "return sqrt(3.0 / (M_PI * phi_c)) * ldexp(1.0, level);",
+     "return sqrt(3.0 / (2.0 * M_PI * phi_c)) * ldexp(1.0, level);",
+     phys.test_tree_closed_form_workload1),
+    # HEALPix (Gorski et al. 2005): pixel centres shifted by half a pixel in phi
+    ("healpix_phi_shift",
+     "*phi = (M_PI / (2.0 * (double)nr)) * ((double)j - 0.5 * (double)(2 - s));",
+     "*phi = (M_PI / (2.0 * (double)nr)) * ((double)j - 0.5 * (double)(1 - s));",
+     lambda O: hp.test_nested_centres_equal_ring_centres(O, 2)),
+    # Eq. e:Erad: the small-optical-depth series of (1 - e^-x)/x with a wrong sign
+    ("phi_series_sign",
+     "if (fabs(x) < 1e-5) return 1.0 - x / 2.0 + x * x / 6.0;",
+     "if (fabs(x) < 1e-5) return 1.0 + x / 2.0 + x * x / 6.0;",
+     phys.test_estimator_in_the_optically_thin_limit),
     # Sec. 2.2 Step 1: seeds injected face by face instead of interleaved
     ("seed_order_by_face",
      "r.pix = (k % 12) * per_face + k / 12;",

@@ -130,6 +130,24 @@ def test_estimator_consistency(oracle):
     assert np.allclose(res.rate, wl.s_H * xn * nH * res.J[0], rtol=1e-14, atol=0)
 
 
+def test_estimator_in_the_optically_thin_limit(oracle):
+    """Optical depths below 1e-5 per segment everywhere (the small-depth series of
+    (1 - e^-x)/x): kappa J still equals the absorbed luminosity to rounding, and
+    J stays within the optical depth of the vacuum J (Eq. e:Erad's chi -> 0
+    limit)."""
+    n = 16
+    xs = [7.3, 8.6, 8.1]
+    thin = I.uniform_workload(n, xs, lum=1.0, s_H=2e-6, n_bins=1)
+    vac = I.uniform_workload(n, xs, lum=1.0, s_H=0.0, n_bins=1)
+    rt = oracle.trace_workload(thin)
+    rv = oracle.trace_workload(vac)
+    kappa = 2e-6
+    assert (kappa * rt.J[0]).sum() == pytest.approx(rt.absorbed[:, 0].sum(), rel=1e-12)
+    m = rv.J[0] > 0
+    assert np.abs(rt.J[0][m] / rv.J[0][m] - 1).max() < 1e-4
+    assert (rt.J[0] <= rv.J[0] * (1 + 1e-15)).all()
+
+
 def test_rate_counts_every_gas_absorption(oracle):
     """Without dust every ionizing photon absorbed is absorbed by neutral
     hydrogen and makes one photoionization (Eq. e:photrate2 with chi_i = n_HI
