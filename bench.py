@@ -111,7 +111,17 @@ def measured_adjoint_valu(workload: int, deterministic: bool):
     return _summary_value("k_adjoint_c3_sq_counters.md", "valu_insts_per_adjoint")
 
 
-def roofline(kernel_s, segments, bytes_per_segment, traffic_bytes, valu_insts, kernel, traffic_unit, launches):
+def measured_arith(workload: int, deterministic: bool, kernel: str):
+    """Floating-point arithmetic VALU instructions (FP64 / FP32 add, mul, fma,
+    transcendental) per 64 segments of `kernel` from the committed instruction-mix
+    summary (fixed-point mode), or None if stale."""
+    if workload != 3 or not deterministic:
+        return None
+    return _summary_value("k_sweep_k_adjoint_c3_valu_mix.md", f"arith_wave_insts_per_64_segments_{kernel}")
+
+
+def roofline(kernel_s, segments, bytes_per_segment, traffic_bytes, valu_insts, kernel, traffic_unit, launches,
+             arith_per_64=None):
     """The roofline block of a kernel: the method's bytes against HBM, the
     measured HBM traffic, and the measured VALU issue against the chip's issue
     rate.  The bound is whichever measured resource is busiest (HBM traffic or
@@ -128,6 +138,12 @@ def roofline(kernel_s, segments, bytes_per_segment, traffic_bytes, valu_insts, k
         tops = valu_insts * 64 / kernel_s / 1e12
         valu = {"achieved": tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (VALU lane-operations)",
                 "frac": tops / VALU_PEAK_TOPS, "wave_insts_per_segment_x64": valu_insts * 64 / segments}
+        if arith_per_64 is not None:
+            # the part of those lane-operations that is floating-point arithmetic
+            # (one lane-operation per segment per wave instruction per 64 segments)
+            at = arith_per_64 * segments / kernel_s / 1e12
+            valu["arithmetic"] = {"lane_ops_per_segment": arith_per_64, "achieved": at,
+                                  "frac": at / VALU_PEAK_TOPS}
     bound = "hbm"
     if valu is not None and (hbm["measured_frac"] is None or valu["frac"] > hbm["measured_frac"]):
         bound = "alu"
@@ -337,7 +353,7 @@ def main():
                     "k_sweep (one launch per HEALPix level)",
                     "GB per k_sweep launch (the average of one trace's per-level launches; traffic_per_pass "
                     "is their sum), rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated",
-                    n_launch_levels)
+                    n_launch_levels, measured_arith(args.workload, wl.deterministic, "k_sweep"))
     roof.update({"bytes_per_segment": BYTES_PER_SEGMENT,
                  "bytes_per_segment_with_accumulator_width":
                      BYTES_PER_SEGMENT_FIXED_POINT if wl.deterministic else BYTES_PER_SEGMENT,
@@ -456,7 +472,7 @@ def main():
                             "k_adjoint (one launch per level, deepest first; one backward walk over every segment)",
                             "GB per k_adjoint launch (the average of one adjoint's per-level launches; "
                             "traffic_per_pass is their sum), rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated",
-                            n_launch_levels)
+                            n_launch_levels, measured_arith(args.workload, wl.deterministic, "k_adjoint"))
         adj_roof["bytes_per_segment"] = ADJOINT_BYTES_PER_SEGMENT
         adjoint = {"ms_per_adjoint": 1e3 * adj_s,
                    "ms_per_forward_with_tree": 1e3 * t_fwd / args.steps,

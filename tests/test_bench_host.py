@@ -84,6 +84,10 @@ def test_roofline_picks_the_busiest_measured_resource():
     r = bench.roofline(t, seg, 40, 0.7 * bench.HBM_PEAK_GBS * 1e9 * t, valu, "k", "u", 8)
     assert r["bound"] == "hbm" and r["unit"] == "GB/s"
     assert r["frac"] == pytest.approx(r["hbm_model"]["frac"])
+    # the arithmetic share of the VALU work, when the instruction mix is known
+    r = bench.roofline(t, seg, 40, 2.0e11, valu, "k", "u", 8, arith_per_64=60.0)
+    assert r["valu_issue"]["arithmetic"]["achieved"] == pytest.approx(60.0 * seg / t / 1e12)
+    assert bench.measured_arith(3, True, "k_sweep") is None or bench.measured_arith(3, True, "k_sweep") > 0
     # no counters: HBM model only, traffic unknown
     r = bench.roofline(t, seg, 40, None, None, "k", "u", 8)
     assert r["bound"] == "hbm" and r["traffic"] is None and r["valu_issue"] is None
