@@ -1538,7 +1538,7 @@ __global__ void k_ion_update(uint64_t N, const float* nH, float* xn, const float
     const double dt = __longlong_as_double((long long)ion[1]);
     if (!(dt > 0.0)) return;
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < N; c += (uint64_t)gridDim.x * blockDim.x) {
-        if (transparent && transparent[c]) continue;  // no interaction with the gas there
+        if (transparent && transparent[c]) continue;  // sink cells keep their ionization state
         const double x0 = (double)xn[c];
         const double a = alpha_B * (double)nH[c] * (1.0 - x0);
         const double s = gamma_scale * (double)J0[c] + a;
